@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the two-step BM3D stage on one MI355X.
+
+Workload: 512x512 grey images (piecewise-smooth gradients + rotated
+textures, seeded synthetic stand-ins for the paper's 512x512 test images),
+AWGN sigma = 25, 8x8 patches, 32x32 search, stride 3, group sizes 16/32.
+A step denoises one batch of images through the batched, graph-captured
+pass (int8 matrix-core matching, BF16 transforms by default); inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line: value = denoised MP/s over the whole job, the
+dominant kernel's roofline (time from HIP events on the launch stream), the
+single-image latency p50/p99, the FP32-form comparison, and the FP64 oracle
+timed on the host cores as the CPU baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "bf16": 2.5e15, "fp16": 2.5e15, "fp32_mfma": 157.3e12, "int8": 5.0e15,
+    # vector FP32 without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+    "fp32_valu": 78.6e12,
+}
+XF = {"fp32": 0, "bf16": 1, "fp16": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def work_models(h, w, S, cnt1, cnt2, c=1):
+    """Algorithmic work per stage for one image (see the design notes):
+    matching = int8 cross terms / FP32 SSD of every window candidate; filters =
+    the dense 3-D transform products at the actual group sizes."""
+    def wlen(L):
+        return min(S, L - 7)
+    cands = len(cnt1) * wlen(h) * wlen(w)
+    n1 = cnt1.astype(np.float64)
+    n2 = cnt2.astype(np.float64)
+    # one dense transform of an n-patch group: 2*64*64*n (2-D DCT) + 2*64*n*n (WHT)
+    xf1 = 2.0 * 64 * n1 * (64 + n1)
+    xf2 = 2.0 * 64 * n2 * (64 + n2)
+    return {
+        "match1": cands * 64 * 2.0,          # int8 ops (multiply + add)
+        "filter1": c * float(np.sum(2 * xf1)),  # forward + inverse
+        "match2": cands * 64 * 3.0,          # FP32 sub + fma per pixel pair
+        "filter2": c * float(np.sum(3 * xf2)),  # noisy + basic forward, inverse
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--xform", default="bf16", choices=list(XF))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the design notes for how the work would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+
+    assert torch.cuda.is_available(), "no GPU"
+    sigma, S, H, W = 25.0, 32, 512, 512
+    B = args.batch
+    log("generating %d synthetic %dx%d images" % (B, H, W))
+    samples = [synth.gray_512(index=i, sigma=sigma) for i in range(B)]
+    imgs = [torch.from_numpy(s.noisy).cuda() for s in samples]
+    outs = [torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(B)]
+
+    p = bm3d.params_default(sigma, xform=XF[args.xform])
+    if not args.no_autotune:
+        t0 = time.time()
+        p = bm3d.autotune(p, None)
+        log("autotune: tile %d refs, persistent %d WG/CU (%.1fs)" % (p.tile_refs, p.persistent_wgs,
+                                                                     time.time() - t0))
+    plan = bm3d.Batch(imgs, outs, [sigma] * B, p)
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    torch.cuda.set_stream(stream)
+    torch.cuda.synchronize()
+    plan.capture(stream)
+
+    for _ in range(args.warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    mp = B * H * W / 1e6
+    value = mp / dt
+    log("batched %s: %.3f ms/step, %.1f MP/s" % (args.xform, dt * 1e3, value))
+
+    # per-stage kernel time with HIP events on the launch stream.  After one
+    # full pass the matching/filter stages can be re-run on valid data (the
+    # filters only add into num/den); the stages that reset or rewrite state
+    # (prep + zero-fill, agg1 + zero-fill, agg2) are timed last.
+    plan.run(stream)
+    stage_ms = {}
+    for st in (1, 2, 4, 5, 0, 3, 6):
+        name = bm3d.STAGES[st]
+        reps = 5
+        plan.run_stages(0, B, st, st, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.run_stages(0, B, st, st, stream)
+        e1.record(stream)
+        e1.synchronize()
+        stage_ms[name] = e0.elapsed_time(e1) / reps
+    log("stage ms: " + ", ".join("%s %.3f" % kv for kv in stage_ms.items()))
+
+    # group sizes of every image (stage entry points, outside the timed region)
+    R = bm3d.num_refs(H, W)
+    work = {"match1": 0.0, "filter1": 0.0, "match2": 0.0, "filter2": 0.0}
+    planar = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    lum = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    lumf = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    i1 = torch.empty((R, p.n_ht), dtype=torch.int32, device="cuda")
+    c1 = torch.empty(R, dtype=torch.int32, device="cuda")
+    i2 = torch.empty((R, p.n_wie), dtype=torch.int32, device="cuda")
+    c2 = torch.empty(R, dtype=torch.int32, device="cuda")
+    num = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    den = torch.empty_like(num)
+    basic = torch.empty_like(num)
+    for im in imgs:
+        bm3d.prepare(im, planar, lum)
+        bm3d.block_match(lum, 1, p, i1, c1)
+        num.zero_()
+        den.zero_()
+        bm3d.collab_filter(planar, None, sigma, 1, i1, c1, p, num, den)
+        bm3d.aggregate(num, den, False, basic)
+        bm3d.luminance(basic, lumf)
+        bm3d.block_match(lumf, 2, p, i2, c2)
+        wm = work_models(H, W, S, c1.cpu().numpy(), c2.cpu().numpy())
+        for k in work:
+            work[k] += wm[k]
+    kinds = {"match1": ("mfma", "int8", PEAK["int8"], "TOP/s"),
+             "match2": ("alu", "fp32_valu", PEAK["fp32_valu"], "TFLOP/s"),
+             "filter1": ("mfma", args.xform, PEAK[args.xform if args.xform != "fp32" else "fp32_mfma"], "TFLOP/s"),
+             "filter2": ("mfma", args.xform, PEAK[args.xform if args.xform != "fp32" else "fp32_mfma"], "TFLOP/s")}
+    dom = max(work, key=lambda k: stage_ms[k])
+    bound, _, peak, unit = kinds[dom]
+    achieved = work[dom] / (stage_ms[dom] * 1e-3)
+    roof = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": unit, "frac": achieved / peak, "traffic": None,
+            "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom]}
+    per_stage = {k: {"ms": stage_ms[k], "frac": (work[k] / (stage_ms[k] * 1e-3)) / kinds[k][2]}
+                 for k in work}
+
+    # single-image latency (plain path) and the FP32 comparison on image 0
+    ws = torch.empty(bm3d.workspace_size(H, W, 1, p), dtype=torch.uint8, device="cuda")
+    lat = []
+    for i in range(30):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bm3d.denoise(imgs[i % B], sigma, p, out=outs[0], workspace=ws)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    lat_ms = sorted(1e3 * x for x in lat[5:])
+    p32 = bm3d.params_default(sigma, xform=0, tile_refs=p.tile_refs)
+    ws32 = torch.empty(bm3d.workspace_size(H, W, 1, p32), dtype=torch.uint8, device="cuda")
+    o32 = bm3d.denoise(imgs[0], sigma, p32, workspace=ws32)
+    olo = bm3d.denoise(imgs[0], sigma, p, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(10):
+        bm3d.denoise(imgs[i % B], sigma, p32, out=outs[1], workspace=ws32)
+    torch.cuda.synchronize()
+    fp32_single = 10 * H * W / 1e6 / (time.perf_counter() - t)
+    clean0 = samples[0].clean
+    psnr32 = synth.psnr(clean0, o32.cpu().numpy())
+    psnrlo = synth.psnr(clean0, olo.cpu().numpy())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        oracle.set_threads(threads)
+        op = oracle.Params.for_sigma(sigma, S)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oracle.denoise(samples[n % B].noisy, sigma, op)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or n >= 4 * B:
+                break
+        cpu = {"value": n * H * W / 1e6 / el, "unit": "MP/s", "cores": threads, "kind": "oracle",
+               "sample": "%d x 512x512 grey sigma=25 images, FP64 C oracle, %.1f s" % (n, el)}
+        log("cpu baseline: %.4f MP/s on %d threads" % (cpu["value"], threads))
+
+    res = {
+        "metric": "denoised MP/s (both BM3D steps, sigma=25)", "value": value, "unit": "MP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.xform + "+int8", "data": "synthetic",
+        "config": {"workload": "512x512 grey, sigma=25, S=32, N1=16, N2=32, stride 3, "
+                               "batch of %d images per step, graph-captured batched pass" % B,
+                   "batch": B, "xform": args.xform, "tile_refs": p.tile_refs,
+                   "persistent_wgs": p.persistent_wgs},
+        "roofline": roof, "stages": per_stage,
+        "latency_ms_single_image": {"p50": float(np.percentile(lat_ms, 50)),
+                                    "p99": float(np.percentile(lat_ms, 99))},
+        "fp32_single_image_MPps": fp32_single,
+        "psnr_db": {"fp32": psnr32, args.xform: psnrlo, "delta": psnrlo - psnr32},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/* bm3d.h -- C ABI of the MI355X (gfx950) BM3D stage.
+ *
+ * The paper (Guo, Davy, Facciolo, Morel, Jin, "Fast, nonlocal and neural: a
+ * lightweight high quality solution to image denoising") denoises
+ * y = x + n, n additive white Gaussian noise of known sigma (eq. (1)), by
+ * running a GPU BM3D first and feeding its output with y to a small residual
+ * CNN (Section II, Fig. 1, eqs. (2)-(3)).  This library is that first stage:
+ * the two-step BM3D method the paper cites (grouping by block matching,
+ * collaborative 3D-transform filtering with hard thresholding then Wiener
+ * shrinkage, Kaiser-weighted aggregation), with colour handled by an
+ * orthonormal opponent transform and grouping on luminance (the CBM3D
+ * variant cited in Table 1), as needed for the colour sets scored by CPSNR.
+ *
+ * Fixed geometry: 8x8 patches, reference patches every 3 pixels along each
+ * axis (positions 0,3,6,..., plus h-8 and w-8), search window of S x S patch
+ * positions centred on the reference (offsets -S/2..S/2-1) and shifted to stay
+ * inside the image.
+ *
+ * Conventions for every entry point:
+ *  - pointers named img/out/planar/lum/basic/num/den/idx/cnt are DEVICE
+ *    pointers owned by the caller; the library never frees them;
+ *  - image layout: interleaved HWC uint8 input, planar [c][h][w] float
+ *    working buffers, HWC float output on the [0,255] scale, unclipped;
+ *  - global patch index = y*w + x of the patch's top-left pixel;
+ *  - work is enqueued asynchronously on `stream` (0 = the null stream); the
+ *    library makes no implicit synchronisation unless BM3D_FLAG_DEBUG_SYNC
+ *    is set in the params, in which case it synchronises the stream after
+ *    each kernel and reports launch/execution errors;
+ *  - arguments are validated on the host before anything is enqueued; on
+ *    failure a negative bm3d_status is returned and nothing is enqueued;
+ *  - no entry point allocates device memory except bm3d_batch_create (at
+ *    plan time) -- the single-image path uses params->workspace.
+ */
+#ifndef BM3D_MI355X_H
+#define BM3D_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bm3d_stream_t; /* = hipStream_t */
+
+typedef enum {
+  BM3D_OK = 0,
+  BM3D_ERR_ARG = -1,         /* invalid argument (null pointer, size, sigma, ...) */
+  BM3D_ERR_UNSUPPORTED = -2, /* valid but unsupported configuration */
+  BM3D_ERR_WORKSPACE = -3,   /* workspace missing or too small */
+  BM3D_ERR_HIP = -4,         /* HIP launch or runtime error */
+  BM3D_ERR_NOMEM = -5        /* device/host allocation failed (plan creation only) */
+} bm3d_status;
+
+/* Arithmetic of the collaborative 3D transforms (DCT 8x8 (x) Walsh-Hadamard).
+ * All forms run the transforms as dense matrix products on the MFMA units
+ * with FP32 accumulation; thresholds, Wiener coefficients, weights and the
+ * aggregation stay FP32 in every form. */
+typedef enum {
+  BM3D_XF_FP32 = 0, /* FP32 operands */
+  BM3D_XF_BF16 = 1, /* BF16 operands, FP32 accumulation */
+  BM3D_XF_FP16 = 2  /* FP16 operands, FP32 accumulation */
+} bm3d_xform;
+
+#define BM3D_FLAG_DEBUG_SYNC 1u
+
+typedef struct {
+  int search_ht, search_wie; /* S of each step, 1..32 */
+  int n_ht, n_wie;           /* max group sizes, powers of two in 1..32 */
+  float lambda_ht;           /* step-1 hard threshold multiplier; keep |c| > lambda*sigma */
+  float tau_ht, tau_wie;     /* a candidate joins only if SSD <= 64*tau (INFINITY: no limit) */
+  float kaiser_beta;         /* Kaiser window parameter of the aggregation (2.0) */
+  int xform;                 /* bm3d_xform */
+  int tile_refs;             /* references per side of the tile one wavefront filters and
+                                aggregates (0 = auto); limited by the LDS budget */
+  int persistent_wgs;        /* batched pass: workgroups per CU (0 = one per tile) */
+  unsigned flags;            /* BM3D_FLAG_* */
+  int32_t* debug_nkept;      /* optional device int32 [c][R]: bm3d_collab_filter step 1
+                                writes each group's number of kept coefficients
+                                (a testing aid; NULL = not written) */
+  void* workspace;           /* device memory for bm3d_denoise, >= bm3d_workspace_size() */
+  size_t workspace_bytes;
+} bm3d_params;
+
+/* Defaults for noise level sigma: S=32 both steps, n 16/32, lambda 2.7,
+ * beta 2.0, FP32 transforms, tau 2500/400 (sigma <= 40) or 5000/3500. */
+int bm3d_params_default(float sigma, bm3d_params* p);
+
+/* Number of reference patches of an h x w image (rows x cols of the grid). */
+int bm3d_num_refs(int h, int w);
+
+/* Device bytes bm3d_denoise needs in params->workspace for this image. */
+size_t bm3d_workspace_size(int h, int w, int c, const bm3d_params* p);
+
+/* Colour/format preparation.  img: HWC uint8 [h][w][c].  planar: float
+ * [c][h][w] -- the grey values (c=1) or the orthonormal opponent channels
+ * (1,1,1)/sqrt3, (1,0,-1)/sqrt2, (1,-2,1)/sqrt6 (c=3).  lum: uint8 [h][w]
+ * step-1 matching luminance -- the grey value or round((R+G+B)/3). */
+int bm3d_prepare(const uint8_t* img, int h, int w, int c, float* planar, uint8_t* lum,
+                 bm3d_stream_t stream);
+
+/* Grouping by block matching (one step).  step 1: src is uint8 [h][w]
+ * (src_is_f32 = 0), distances are exact integer SSDs computed as
+ * |p|^2 + |q|^2 - 2 p.q on int8 matrix cores (values shifted by -128).
+ * step 2: src is float [h][w] (src_is_f32 = 1), FP32 SSDs.  For every
+ * reference r (row-major over the grid) the group is r followed by the
+ * other window candidates with SSD <= 64*tau in increasing (SSD, index)
+ * order, truncated to n = the largest power of two <= min(1 + #passing,
+ * n_max), n_max = n_ht or n_wie.  idx: int32 [R][n_max], unused slots -1;
+ * cnt: int32 [R] = n. */
+int bm3d_block_match(const void* src, int src_is_f32, int h, int w, int step,
+                     const bm3d_params* p, int32_t* idx, int32_t* cnt, bm3d_stream_t stream);
+
+/* Collaborative filtering of all groups, accumulated (+=) into num/den
+ * (planar float [c][h][w]).  noisy: planar working channels.  step 1: 3D
+ * spectrum hard-thresholded at lambda*sigma (kept iff |s| > lambda*sigma),
+ * group weight 1/N_kept (1 if none kept); basic must be NULL.  step 2:
+ * empirical Wiener shrinkage W = B^2/(B^2+sigma^2) of the noisy spectrum, B
+ * the spectrum of `basic` (planar) over the same patches, weight 1/sum W^2
+ * (1 if 0).  Weights are per channel; each filtered patch adds
+ * w*K(u)K(v)*value into num and w*K(u)K(v) into den (K = Kaiser window). */
+int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int c,
+                       float sigma, int step, const int32_t* idx, const int32_t* cnt,
+                       const bm3d_params* p, float* num, float* den, bm3d_stream_t stream);
+
+/* out = num/den.  final_step = 0: out is planar [c][h][w] (the basic
+ * estimate).  final_step = 1: out is HWC [h][w][c], opponent channels mapped
+ * back to RGB with the transpose of the opponent matrix. */
+int bm3d_aggregate(const float* num, const float* den, int h, int w, int c, int final_step,
+                   float* out, bm3d_stream_t stream);
+
+/* Step-2 matching luminance from a planar basic estimate: the grey channel,
+ * or the first opponent channel / sqrt3 (= mean of R,G,B).  lum: float [h][w]. */
+int bm3d_luminance(const float* basic, int h, int w, int c, float* lum, bm3d_stream_t stream);
+
+/* Whole two-step denoiser on one image.  img: HWC uint8; out: HWC float.
+ * Uses params->workspace (>= bm3d_workspace_size bytes). */
+int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_params* params,
+                 float* out, bm3d_stream_t stream);
+
+/* ---- batched pass: many images of different sizes in one launch per stage ----
+ * A plan fixes the image shapes and sigmas; it owns device memory for every
+ * image's working buffers and the device descriptor tables (allocated at
+ * creation).  Input/output pointers can be re-bound between runs without
+ * re-planning.  bm3d_batch_run enqueues the whole two-step pass over all
+ * images as persistent kernels that walk a tile list; bm3d_batch_capture
+ * records it into a HIP graph once and bm3d_batch_launch replays it. */
+typedef struct {
+  const uint8_t* img; /* device HWC uint8 */
+  float* out;         /* device HWC float */
+  int h, w, c;
+  float sigma;
+} bm3d_image_desc;
+
+typedef struct bm3d_batch bm3d_batch;
+
+int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_params* p,
+                      bm3d_batch** plan);
+size_t bm3d_batch_device_bytes(const bm3d_batch* plan);
+/* Re-bind image i's input/output pointers (shape and sigma stay); takes
+ * effect for the next run or graph launch on `stream`. */
+int bm3d_batch_set_io(bm3d_batch* plan, int i, const uint8_t* img, float* out,
+                      bm3d_stream_t stream);
+int bm3d_batch_run(bm3d_batch* plan, bm3d_stream_t stream);
+int bm3d_batch_capture(bm3d_batch* plan, bm3d_stream_t stream);
+int bm3d_batch_launch(bm3d_batch* plan, bm3d_stream_t stream);
+/* Run only the stages [first, last] (0..6: prep, match1, filter1, agg1,
+ * match2, filter2, agg2) for images [i0, i1) of the plan: the unit of
+ * stage-level continuous batching in the serving loop. */
+int bm3d_batch_run_stages(bm3d_batch* plan, int i0, int i1, int first, int last,
+                          bm3d_stream_t stream);
+int bm3d_batch_destroy(bm3d_batch* plan);
+
+/* Measures the candidate filter tile shapes / persistent grid sizes on the
+ * current device for these params and writes the fastest into p
+ * (tile_refs, persistent_wgs).  cache_path (optional) is a JSON file keyed by
+ * device architecture, search size, max group size and transform form, read
+ * before measuring and updated after.  Synchronises the device. */
+int bm3d_autotune(bm3d_params* p, const char* cache_path);
+
+const char* bm3d_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

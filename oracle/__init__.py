@@ -54,7 +54,7 @@ def lib():
         L.orc_match_u8.argtypes = [u8p, ci, ci, ci, ci, cd, i32p, i32p]
         L.orc_match_f64.argtypes = [f64p, ci, ci, ci, ci, cd, i32p, i32p]
         L.orc_filter.argtypes = [f64p, vp, ci, ci, ci, cd, ci, i32p, i32p, ci,
-                                 vp, f64p, f64p, vp]
+                                 vp, f64p, f64p, vp, vp]
         L.orc_aggregate.argtypes = [f64p, f64p, ci, ci, ci, ci, f64p]
         L.orc_luminance_f64.argtypes = [f64p, ci, ci, ci, f64p]
         L.orc_denoise.argtypes = [u8p, ci, ci, ci, cd, vp, f64p, vp, vp, vp, vp, vp]
@@ -185,7 +185,9 @@ def match_f64(lum, search: int, nmax: int, tau: float):
 
 def collab_filter(noisy_planar, basic_planar, sigma: float, step: int, idx, cnt,
                   params: Params, want_margin: bool = False):
-    """Returns (num, den[, margin]) with num/den planar [c,h,w] (fresh, not +=)."""
+    """Returns (num, den[, margin, nkept]) with num/den planar [c,h,w] (fresh,
+    not +=); with want_margin also the per-reference distance of the closest
+    coefficient to the hard threshold and N_kept per [channel, reference]."""
     noisy = np.ascontiguousarray(noisy_planar, np.float64)
     c, h, w = noisy.shape
     basic = None if basic_planar is None else np.ascontiguousarray(basic_planar, np.float64)
@@ -194,12 +196,14 @@ def collab_filter(noisy_planar, basic_planar, sigma: float, step: int, idx, cnt,
     num = np.zeros((c, h, w))
     den = np.zeros((c, h, w))
     margin = np.zeros(len(cnt)) if want_margin else None
+    nkept = np.zeros((c, len(cnt)), np.int32) if want_margin else None
     cp = params._c()
     lib().orc_filter(noisy.reshape(-1), None if basic is None else basic.ctypes.data,
                      h, w, c, sigma, step, idx.reshape(-1), cnt, idx.shape[1],
                      ctypes.addressof(cp), num.reshape(-1), den.reshape(-1),
-                     None if margin is None else margin.ctypes.data)
-    return (num, den, margin) if want_margin else (num, den)
+                     None if margin is None else margin.ctypes.data,
+                     None if nkept is None else nkept.ctypes.data)
+    return (num, den, margin, nkept) if want_margin else (num, den)
 
 
 def aggregate(num, den, final_step: bool):

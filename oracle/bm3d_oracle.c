@@ -296,10 +296,12 @@ void orc_match_f64(const double* lum, int h, int w, int S, int nmax, double tau,
  * patch is added into num with weight w*K(u)K(v) and w*K(u)K(v) into den,
  * K the Kaiser window.  num/den are accumulated (+=).  margin (optional,
  * step 1) receives, per reference, min over channels and coefficients of
- * ||s| - lambda*sigma|: how close the group is to a threshold decision. */
+ * ||s| - lambda*sigma|: how close the group is to a threshold decision;
+ * nkept (optional, step 1) receives N_kept per channel and reference,
+ * laid out [c][R]. */
 void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
                 double sigma, int step, const int32_t* idx, const int32_t* cnt, int nmax,
-                const orc_params* p, double* num, double* den, double* margin) {
+                const orc_params* p, double* num, double* den, double* margin, int32_t* nkept) {
   int32_t rr[4096], rc[4096];
   int nr = orc_ref_positions(h, rr), nc = orc_ref_positions(w, rc);
   size_t hw = (size_t)h * w;
@@ -344,6 +346,7 @@ void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
               s[e] = 0.0;
           }
           weight = kept >= 1 ? 1.0 / kept : 1.0;
+          if (nkept) nkept[(size_t)k * nr * nc + r] = kept;
         } else {
           orc_transform3d(gb, n, sb, 0);
           double sw2 = 0.0;
@@ -425,14 +428,14 @@ int orc_denoise(const uint8_t* img, int h, int w, int c, double sigma, const orc
 
   orc_prepare(img, h, w, c, planar, lum);
   orc_match_u8(lum, h, w, p->search_ht, p->n_ht, p->tau_ht, i1, c1);
-  orc_filter(planar, NULL, h, w, c, sigma, 1, i1, c1, p->n_ht, p, num, den, NULL);
+  orc_filter(planar, NULL, h, w, c, sigma, 1, i1, c1, p->n_ht, p, num, den, NULL, NULL);
   orc_aggregate(num, den, h, w, c, 0, basic);
   if (basic_planar) memcpy(basic_planar, basic, sizeof(double) * c * hw);
   orc_luminance_f64(basic, h, w, c, lum2);
   orc_match_f64(lum2, h, w, p->search_wie, p->n_wie, p->tau_wie, i2, c2);
   memset(num, 0, sizeof(double) * c * hw);
   memset(den, 0, sizeof(double) * c * hw);
-  orc_filter(planar, basic, h, w, c, sigma, 2, i2, c2, p->n_wie, p, num, den, NULL);
+  orc_filter(planar, basic, h, w, c, sigma, 2, i2, c2, p->n_wie, p, num, den, NULL, NULL);
   orc_aggregate(num, den, h, w, c, 1, out);
 
   free(planar);

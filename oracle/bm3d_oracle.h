@@ -54,7 +54,7 @@ void orc_match_f64(const double* lum, int h, int w, int S, int nmax, double tau,
                    int32_t* idx, int32_t* cnt);
 void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
                 double sigma, int step, const int32_t* idx, const int32_t* cnt, int nmax,
-                const orc_params* p, double* num, double* den, double* margin);
+                const orc_params* p, double* num, double* den, double* margin, int32_t* nkept);
 void orc_aggregate(const double* num, const double* den, int h, int w, int c,
                    int final_step, double* out);
 void orc_luminance_f64(const double* basic, int h, int w, int c, double* lum);

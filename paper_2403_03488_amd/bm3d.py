@@ -1,0 +1,261 @@
+"""Python binding of the C ABI in include/bm3d.h (ctypes).
+
+Argument marshalling only: every step of the denoiser runs in the HIP
+library (libbm3d_mi355x.so, built from csrc/).  Device memory and streams
+come from PyTorch (ROCm); tensors are passed as raw device pointers.  There
+is no fallback: importing this module fails if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbm3d_mi355x.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("HIP library %s is not built (run __graft_entry__.build())" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+XF_FP32, XF_BF16, XF_FP16 = 0, 1, 2
+FLAG_DEBUG_SYNC = 1
+STAGES = ("prep", "match1", "filter1", "agg1", "match2", "filter2", "agg2")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("search_ht", ctypes.c_int), ("search_wie", ctypes.c_int),
+                ("n_ht", ctypes.c_int), ("n_wie", ctypes.c_int),
+                ("lambda_ht", ctypes.c_float), ("tau_ht", ctypes.c_float),
+                ("tau_wie", ctypes.c_float), ("kaiser_beta", ctypes.c_float),
+                ("xform", ctypes.c_int), ("tile_refs", ctypes.c_int),
+                ("persistent_wgs", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("debug_nkept", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+    def copy(self) -> "Params":
+        q = Params()
+        ctypes.pointer(q)[0] = self
+        return q
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
+                ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
+
+
+_vp, _i, _f, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+_PP = ctypes.POINTER(Params)
+_SIGS = {
+    "bm3d_params_default": (_i, [_f, _PP]),
+    "bm3d_num_refs": (_i, [_i, _i]),
+    "bm3d_workspace_size": (_sz, [_i, _i, _i, _PP]),
+    "bm3d_prepare": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "bm3d_block_match": (_i, [_vp, _i, _i, _i, _i, _PP, _vp, _vp, _vp]),
+    "bm3d_collab_filter": (_i, [_vp, _vp, _i, _i, _i, _f, _i, _vp, _vp, _PP, _vp, _vp, _vp]),
+    "bm3d_aggregate": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp]),
+    "bm3d_luminance": (_i, [_vp, _i, _i, _i, _vp, _vp]),
+    "bm3d_denoise": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
+    "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
+    "bm3d_batch_device_bytes": (_sz, [_vp]),
+    "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "bm3d_batch_run": (_i, [_vp, _vp]),
+    "bm3d_batch_capture": (_i, [_vp, _vp]),
+    "bm3d_batch_launch": (_i, [_vp, _vp]),
+    "bm3d_batch_run_stages": (_i, [_vp, _i, _i, _i, _i, _vp]),
+    "bm3d_batch_destroy": (_i, [_vp]),
+    "bm3d_autotune": (_i, [_PP, ctypes.c_char_p]),
+    "bm3d_strerror": (ctypes.c_char_p, [_i]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class BM3DError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, _lib.bm3d_strerror(status).decode(), status))
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise BM3DError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return t.data_ptr()
+
+
+def params_default(sigma: float, **overrides) -> Params:
+    p = Params()
+    _check(_lib.bm3d_params_default(float(sigma), ctypes.byref(p)), "bm3d_params_default")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def num_refs(h: int, w: int) -> int:
+    return _lib.bm3d_num_refs(h, w)
+
+
+def workspace_size(h: int, w: int, c: int, p: Params) -> int:
+    return _lib.bm3d_workspace_size(h, w, c, ctypes.byref(p))
+
+
+def strerror(status: int) -> str:
+    return _lib.bm3d_strerror(status).decode()
+
+
+# ------------------------------------------------------------ stage calls ---
+
+def prepare(img, planar, lum, stream=None):
+    """img: uint8 [h,w] or [h,w,3]; planar: float32 [c,h,w]; lum: uint8 [h,w]."""
+    torch = _torch()
+    h, w = img.shape[0], img.shape[1]
+    c = 1 if img.dim() == 2 else img.shape[2]
+    _check(_lib.bm3d_prepare(_ptr(img, torch.uint8, "img"), h, w, c,
+                             _ptr(planar, torch.float32, "planar"), _ptr(lum, torch.uint8, "lum"),
+                             _stream(stream)), "bm3d_prepare")
+
+
+def block_match(src, step: int, p: Params, idx, cnt, stream=None):
+    torch = _torch()
+    h, w = src.shape
+    is_f32 = 1 if src.dtype == torch.float32 else 0
+    _check(_lib.bm3d_block_match(_ptr(src, None, "src"), is_f32, h, w, step, ctypes.byref(p),
+                                 _ptr(idx, torch.int32, "idx"), _ptr(cnt, torch.int32, "cnt"),
+                                 _stream(stream)), "bm3d_block_match")
+
+
+def collab_filter(noisy, basic, sigma: float, step: int, idx, cnt, p: Params, num, den,
+                  stream=None):
+    torch = _torch()
+    c, h, w = noisy.shape
+    _check(_lib.bm3d_collab_filter(_ptr(noisy, torch.float32, "noisy"),
+                                   _ptr(basic, torch.float32, "basic"), h, w, c, float(sigma),
+                                   step, _ptr(idx, torch.int32, "idx"),
+                                   _ptr(cnt, torch.int32, "cnt"), ctypes.byref(p),
+                                   _ptr(num, torch.float32, "num"),
+                                   _ptr(den, torch.float32, "den"), _stream(stream)),
+           "bm3d_collab_filter")
+
+
+def aggregate(num, den, final_step: bool, out, stream=None):
+    torch = _torch()
+    c, h, w = num.shape
+    _check(_lib.bm3d_aggregate(_ptr(num, torch.float32, "num"), _ptr(den, torch.float32, "den"),
+                               h, w, c, 1 if final_step else 0, _ptr(out, torch.float32, "out"),
+                               _stream(stream)), "bm3d_aggregate")
+
+
+def luminance(basic, lum, stream=None):
+    torch = _torch()
+    c, h, w = basic.shape
+    _check(_lib.bm3d_luminance(_ptr(basic, torch.float32, "basic"), h, w, c,
+                               _ptr(lum, torch.float32, "lum"), _stream(stream)), "bm3d_luminance")
+
+
+def denoise(img, sigma: float, p: Params | None = None, out=None, workspace=None, stream=None):
+    """Two-step denoiser on one device image (uint8 [h,w] or [h,w,3]).
+    Returns a float32 device tensor of the same shape on the [0,255] scale."""
+    torch = _torch()
+    h, w = img.shape[0], img.shape[1]
+    c = 1 if img.dim() == 2 else img.shape[2]
+    p = (p or params_default(sigma)).copy()
+    need = workspace_size(h, w, c, p)
+    if need == 0:
+        raise BM3DError(-1, "bm3d_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
+    p.workspace = workspace.data_ptr()
+    p.workspace_bytes = workspace.numel()
+    if out is None:
+        out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+    _check(_lib.bm3d_denoise(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma),
+                             ctypes.byref(p), _ptr(out, torch.float32, "out"), _stream(stream)),
+           "bm3d_denoise")
+    return out
+
+
+def autotune(p: Params, cache_path: str | None = None) -> Params:
+    q = p.copy()
+    _check(_lib.bm3d_autotune(ctypes.byref(q), cache_path.encode() if cache_path else None),
+           "bm3d_autotune")
+    return q
+
+
+# ---------------------------------------------------------------- batches ---
+
+class Batch:
+    """A batched plan over many images of different shapes (bm3d_batch_*)."""
+
+    def __init__(self, images, outs, sigmas, p: Params):
+        self.n = len(images)
+        arr = (ImageDesc * self.n)()
+        for i, (im, o, s) in enumerate(zip(images, outs, sigmas)):
+            c = 1 if im.dim() == 2 else im.shape[2]
+            arr[i] = ImageDesc(_ptr(im, None, "img"), _ptr(o, None, "out"), im.shape[0],
+                               im.shape[1], c, float(s))
+        self._keep = (images, outs)
+        self._h = ctypes.c_void_p()
+        _check(_lib.bm3d_batch_create(arr, self.n, ctypes.byref(p), ctypes.byref(self._h)),
+               "bm3d_batch_create")
+
+    @property
+    def device_bytes(self) -> int:
+        return _lib.bm3d_batch_device_bytes(self._h)
+
+    def set_io(self, i: int, img, out, stream=None):
+        _check(_lib.bm3d_batch_set_io(self._h, i, _ptr(img, None, "img"), _ptr(out, None, "out"),
+                                      _stream(stream)), "bm3d_batch_set_io")
+
+    def run(self, stream=None):
+        _check(_lib.bm3d_batch_run(self._h, _stream(stream)), "bm3d_batch_run")
+
+    def run_stages(self, i0: int, i1: int, first: int, last: int, stream=None):
+        _check(_lib.bm3d_batch_run_stages(self._h, i0, i1, first, last, _stream(stream)),
+               "bm3d_batch_run_stages")
+
+    def capture(self, stream=None):
+        _check(_lib.bm3d_batch_capture(self._h, _stream(stream)), "bm3d_batch_capture")
+
+    def launch(self, stream=None):
+        _check(_lib.bm3d_batch_launch(self._h, _stream(stream)), "bm3d_batch_launch")
+
+    def close(self):
+        if self._h:
+            _lib.bm3d_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def library_symbols():
+    """Names of the entry points this binding binds (all declared in bm3d.h)."""
+    return sorted(_SIGS)

@@ -1,0 +1,245 @@
+// Device-side building blocks of the gfx950 BM3D stage: geometry of the
+// reference grid and search windows, wavefront (64-lane) primitives, and the
+// 16x16 MFMA fragment abstraction used by the collaborative transforms.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bm3d {
+
+constexpr int kP = 8;       // patch side
+constexpr int kStride = 3;  // reference stride
+constexpr int kMaxS = 32;   // largest search window side (10-bit window index)
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ geometry ---
+// Reference positions along an axis: 0,3,6,... <= len-8, plus len-8.
+__host__ __device__ inline int ref_count_1d(int len) {
+  int last = len - kP;
+  return last / kStride + 1 + ((last % kStride) ? 1 : 0);
+}
+__host__ __device__ inline int ref_pos(int i, int len) {
+  int last = len - kP, p = kStride * i;
+  return p > last ? last : p;
+}
+// S consecutive candidate positions [a, a+n) nominally centred on i (offsets
+// -S/2..S/2-1), shifted to stay inside [0, len-8]; all positions if fewer.
+__host__ __device__ inline void window_1d(int i, int len, int S, int& a, int& n) {
+  int npos = len - kP + 1;
+  if (npos <= S) {
+    a = 0;
+    n = npos;
+    return;
+  }
+  int lo = i - S / 2;
+  lo = lo < 0 ? 0 : lo;
+  lo = lo > npos - S ? npos - S : lo;
+  a = lo;
+  n = S;
+}
+
+// Per-image descriptor shared by all stages (device pointers).
+struct ImgDesc {
+  const uint8_t* img;  // HWC uint8 input
+  float* out;          // HWC float output
+  float* planar;       // [c][h][w] working channels (grey / opponent)
+  uint8_t* lum8;       // [h][w] step-1 matching luminance
+  float* lumf;         // [h][w] step-2 matching luminance
+  float* basic;        // [c][h][w] basic estimate
+  float* num;          // [c][h][w] aggregation numerator
+  float* den;          // [c][h][w] aggregation denominator
+  int32_t* idx1;       // [R][n_ht]
+  int32_t* cnt1;       // [R]
+  int32_t* idx2;       // [R][n_wie]
+  int32_t* cnt2;       // [R]
+  int32_t* nkept;      // optional [c][R] step-1 kept-coefficient counts
+  int h, w, c, nr, nc;
+  float sigma;
+  float lam_sigma;     // lambda * sigma
+  uint32_t thr1;       // step-1 integer SSD bound floor(64 tau_ht), <= 2^22-1
+  float thr2;          // step-2 SSD bound 64 tau_wie
+};
+
+// Parameters shared by every image of a launch.
+struct KParams {
+  int S1, S2;       // search sides
+  int n1, n2;       // max group sizes
+  int tile;         // filter tile side in references
+  float kaiser[8];  // 1-D Kaiser window
+};
+
+// ----------------------------------------------------- wave primitives ---
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ inline uint32_t shfl_xor_u32(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
+__device__ inline uint32_t shfl_u32(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+  uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = shfl_u32((uint32_t)v, src), hi = shfl_u32((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+template <class K> __device__ inline K shfl_xor_k(K v, int m);
+template <> __device__ inline uint32_t shfl_xor_k<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
+template <> __device__ inline uint64_t shfl_xor_k<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
+template <class K> __device__ inline K shfl_k(K v, int s);
+template <> __device__ inline uint32_t shfl_k<uint32_t>(uint32_t v, int s) { return shfl_u32(v, s); }
+template <> __device__ inline uint64_t shfl_k<uint64_t>(uint64_t v, int s) { return shfl_u64(v, s); }
+
+template <class K> __device__ inline K kmin(K a, K b) { return a < b ? a : b; }
+template <class K> __device__ inline K kmax(K a, K b) { return a < b ? b : a; }
+
+// Bitonic sort of one key per lane across the wave, ascending by lane.
+template <class K> __device__ inline K wave_sort(K v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      K o = shfl_xor_k<K>(v, j);
+      bool up = (l & k) == 0;
+      bool lower = (l & j) == 0;
+      v = (lower == up) ? kmin(v, o) : kmax(v, o);
+    }
+  }
+  return v;
+}
+
+// a, b ascending across lanes -> the 64 smallest of a U b, ascending.
+template <class K> __device__ inline K wave_merge_low(K a, K b) {
+  const int l = lane_id();
+  K m = kmin(a, shfl_k<K>(b, 63 - l));
+#pragma unroll
+  for (int j = 32; j > 0; j >>= 1) {
+    K o = shfl_xor_k<K>(m, j);
+    m = (l & j) ? kmax(m, o) : kmin(m, o);
+  }
+  return m;
+}
+
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+__device__ inline float wave_sum_f(float v) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Group selection shared by both matching steps.  Each lane holds 16 keys
+// (kmax<K> = not a candidate); keys order candidates by (distance, window
+// index).  Returns the group size n = largest power of two <=
+// min(1 + #candidates, nmax); lanes 0..n-2 receive the n-1 smallest keys in
+// ascending order in `sel`.  `buf` is wave-private LDS scratch of at least
+// as many entries as there are candidates (may alias the keys' source).
+template <class K>
+__device__ int select_group(const K (&k)[16], int nmax, K* buf, K& sel) {
+  const K NONE = ~(K)0;
+  const int l = lane_id();
+  int npass = 0;
+#pragma unroll
+  for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[t] != NONE));
+  int m = 1 + npass < nmax ? 1 + npass : nmax;
+  int n = 1 << (31 - __clz(m));
+  sel = NONE;
+  if (n == 1) return 1;
+  const int want = n - 1;
+  // Upper bound on the want-th smallest key: the want-th smallest of the
+  // per-lane minima (those are `want` distinct candidates at or below it).
+  K mn = k[0];
+#pragma unroll
+  for (int t = 1; t < 16; t++) mn = kmin(mn, k[t]);
+  K theta = shfl_k<K>(wave_sort(mn), want - 1);
+  // compact the survivors (candidates with key <= theta) into buf
+  int base = 0;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    bool p = k[t] <= theta && k[t] != NONE;
+    uint64_t b = __ballot(p);
+    if (p) buf[base + __popcll(b & lt)] = k[t];
+    base += __popcll(b);
+  }
+  wave_lds_sync();
+  K res = NONE;
+  for (int c0 = 0; c0 < base; c0 += 64) {
+    K v = (c0 + l < base) ? buf[c0 + l] : NONE;
+    v = wave_sort(v);
+    res = (c0 == 0) ? v : wave_merge_low(res, v);
+  }
+  wave_lds_sync();
+  sel = res;
+  return n;
+}
+
+// ------------------------------------------------- MFMA 16x16 fragments ---
+// A 16x16 operand tile held as 4 values per lane: lane l, value v stands for
+// (row or column l%16, contraction index 4*(l/16)+v).  The accumulator tile
+// (float4) has lane l, value v = element (row 4*(l/16)+v, column l%16), so an
+// accumulator can feed the next product directly: as its B operand (same
+// matrix) or as its A operand (the transpose).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+struct XF32 {
+  typedef f32x4 frag;
+  static __device__ inline frag cvt(f32x4 a) { return a; }
+  static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
+    return c;
+  }
+};
+struct XBF16 {
+  typedef bf16x4 frag;
+  static __device__ inline frag cvt(f32x4 a) {
+    frag r;
+    r[0] = (__bf16)a[0];
+    r[1] = (__bf16)a[1];
+    r[2] = (__bf16)a[2];
+    r[3] = (__bf16)a[3];
+    return r;
+  }
+  static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+struct XF16 {
+  typedef f16x4 frag;
+  static __device__ inline frag cvt(f32x4 a) {
+    frag r;
+    r[0] = (_Float16)a[0];
+    r[1] = (_Float16)a[1];
+    r[2] = (_Float16)a[2];
+    r[3] = (_Float16)a[3];
+    return r;
+  }
+  static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ inline f32x4 zero4() {
+  f32x4 z = {0.f, 0.f, 0.f, 0.f};
+  return z;
+}
+
+}  // namespace bm3d

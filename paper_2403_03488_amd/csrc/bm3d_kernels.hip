@@ -1,0 +1,979 @@
+// gfx950 kernels of the BM3D stage.
+//
+// Stages of one image (all enqueued on one stream, no host synchronisation):
+//   prep      HWC uint8 -> planar working channels + uint8 matching luminance
+//   match1    grouping on the uint8 luminance: exact integer SSDs from int8
+//             MFMA cross terms, wavefront top-N selection
+//   filter1   3D DCT (x) Walsh-Hadamard as a chain of MFMA products, hard
+//             threshold, inverse, Kaiser-weighted aggregation in LDS
+//   agg1      basic estimate = num/den, step-2 luminance
+//   match2    grouping on the FP32 basic luminance (direct FP32 SSDs)
+//   filter2   Wiener shrinkage with the basic estimate as pilot
+//   agg2      final estimate = num/den, opponent -> RGB, HWC
+// Every stage exists as a single-image kernel (descriptor by value, one
+// workgroup per tile) and a batched kernel that walks a device work list of
+// (image, tile) items with a grid-stride loop (persistent when the grid is
+// smaller than the list).
+#include "bm3d_device.h"
+#include "bm3d_launch.h"
+
+#include <algorithm>
+
+namespace bm3d {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = kThreads * 4;  // pixels per elementwise work item
+constexpr uint32_t kNone32 = 0xffffffffu;
+constexpr uint64_t kNone64 = ~0ull;
+
+// Orthonormal opponent transform rows (1,1,1)/sqrt3, (1,0,-1)/sqrt2, (1,-2,1)/sqrt6.
+#define OPP_A 0.57735026918962576f
+#define OPP_B 0.70710678118654752f
+#define OPP_C 0.40824829046386302f
+
+// Centre subtracted from a working channel before the transforms (only the
+// 3-D DC coefficient depends on it, and it is restored exactly there).
+__device__ inline float channel_centre(int c, int ch) {
+  return c == 1 ? 128.f : (ch == 0 ? 128.f * 1.7320508075688772f : 0.f);
+}
+
+// =================================================================== prep ==
+__device__ void prep_chunk(const ImgDesc& d, int chunk) {
+  const size_t hw = (size_t)d.h * d.w;
+  const size_t p0 = (size_t)chunk * kChunk;
+  for (int k = 0; k < 4; k++) {
+    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
+    if (p >= hw) return;
+    if (d.c == 1) {
+      uint8_t v = d.img[p];
+      d.planar[p] = (float)v;
+      d.lum8[p] = v;
+    } else {
+      int r = d.img[3 * p], g = d.img[3 * p + 1], b = d.img[3 * p + 2];
+      d.planar[p] = (float)(r + g + b) * OPP_A;
+      d.planar[hw + p] = (float)(r - b) * OPP_B;
+      d.planar[2 * hw + p] = (float)(r - 2 * g + b) * OPP_C;
+      d.lum8[p] = (uint8_t)((r + g + b + 1) / 3);
+    }
+  }
+}
+
+__device__ void fill_chunk(const ImgDesc& d, int chunk) {
+  const size_t n = (size_t)d.c * d.h * d.w;
+  const size_t p0 = (size_t)chunk * kChunk;
+  for (int k = 0; k < 4; k++) {
+    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
+    if (p < n) {
+      d.num[p] = 0.f;
+      d.den[p] = 0.f;
+    }
+  }
+}
+
+// basic = num/den (planar); step-2 luminance (grey, or channel 0 / sqrt3)
+__device__ void agg1_chunk(const ImgDesc& d, int chunk) {
+  const size_t hw = (size_t)d.h * d.w;
+  const size_t p0 = (size_t)chunk * kChunk;
+  for (int k = 0; k < 4; k++) {
+    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
+    if (p >= hw) return;
+    for (int ch = 0; ch < d.c; ch++) {
+      float b = d.num[ch * hw + p] / d.den[ch * hw + p];
+      d.basic[ch * hw + p] = b;
+      if (ch == 0 && d.lumf) d.lumf[p] = d.c == 1 ? b : b * OPP_A;
+    }
+  }
+}
+
+// step-2 luminance from a planar basic estimate
+__device__ void lum_chunk(const ImgDesc& d, int chunk) {
+  const size_t hw = (size_t)d.h * d.w;
+  const size_t p0 = (size_t)chunk * kChunk;
+  for (int k = 0; k < 4; k++) {
+    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
+    if (p >= hw) return;
+    float b = d.basic[p];
+    d.lumf[p] = d.c == 1 ? b : b * OPP_A;
+  }
+}
+
+// final = num/den, opponent -> RGB via the transpose, HWC
+__device__ void agg2_chunk(const ImgDesc& d, int chunk) {
+  const size_t hw = (size_t)d.h * d.w;
+  const size_t p0 = (size_t)chunk * kChunk;
+  for (int k = 0; k < 4; k++) {
+    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
+    if (p >= hw) return;
+    if (d.c == 1) {
+      d.out[p] = d.num[p] / d.den[p];
+    } else {
+      float e0 = d.num[p] / d.den[p];
+      float e1 = d.num[hw + p] / d.den[hw + p];
+      float e2 = d.num[2 * hw + p] / d.den[2 * hw + p];
+      d.out[3 * p] = OPP_A * e0 + OPP_B * e1 + OPP_C * e2;
+      d.out[3 * p + 1] = OPP_A * e0 - 2.f * OPP_C * e2;
+      d.out[3 * p + 2] = OPP_A * e0 - OPP_B * e1 + OPP_C * e2;
+    }
+  }
+}
+
+// ============================================================ block geometry
+// A matching block is a 4x4 set of references; the union of their search
+// windows spans at most (9+S) x (9+S) candidate positions.
+struct BlockGeom {
+  int ri0, ci0, nri, nci;  // first ref row/col and counts (<= 4 / <= tile)
+  int uy0, ux0;            // union window origin (pixels)
+  int ny, nx;              // union window extent (candidate positions)
+  int SH, SW;              // per-reference window extent
+};
+
+__device__ inline BlockGeom block_geom(int h, int w, int nr, int nc, int S, int side, int by,
+                                       int bx) {
+  BlockGeom g;
+  g.ri0 = side * by;
+  g.ci0 = side * bx;
+  g.nri = min(side, nr - g.ri0);
+  g.nci = min(side, nc - g.ci0);
+  int a1, n1, a2, n2;
+  window_1d(ref_pos(g.ri0, h), h, S, a1, n1);
+  window_1d(ref_pos(g.ri0 + g.nri - 1, h), h, S, a2, n2);
+  g.uy0 = a1;
+  g.ny = a2 - a1 + n1;
+  g.SH = n1;
+  window_1d(ref_pos(g.ci0, w), w, S, a1, n1);
+  window_1d(ref_pos(g.ci0 + g.nci - 1, w), w, S, a2, n2);
+  g.ux0 = a1;
+  g.nx = a2 - a1 + n1;
+  g.SW = n1;
+  return g;
+}
+
+// =========================================================== step-1 match ==
+// LDS: int8 luminance region [(S+16) rows][64 B], candidate norms
+// [(S+9)][48] int32, keys [16 refs][SH*SW] uint32 (also row-sum scratch).
+__host__ __device__ inline size_t match1_lds_bytes(int S) {
+  size_t keys = (size_t)16 * S * S * 4, rs = (size_t)(S + 16) * 48 * 4;
+  return (size_t)(S + 16) * 64 + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
+}
+
+// 8 bytes starting at byte offset off of an LDS buffer (dword-aligned base).
+__device__ inline uint64_t lds_bytes8(const uint8_t* base, int off) {
+  const uint32_t* p = (const uint32_t*)(base + (off & ~3));
+  uint32_t d0 = p[0], d1 = p[1], d2 = p[2];
+  uint32_t sh = (uint32_t)(off & 3) * 8u;
+  uint32_t lo = __builtin_amdgcn_alignbit(d1, d0, sh);
+  uint32_t hi = __builtin_amdgcn_alignbit(d2, d1, sh);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
+  const int S = kp.S1, nmax = kp.n1;
+  const int h = d.h, w = d.w;
+  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int q = l >> 4, col = l & 15;
+  const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
+  const int SH = g.SH, SW = g.SW, SS = SH * SW;
+  const int RR = g.ny + 7;
+  const int nblk = (g.nx + 15) >> 4;
+  const int NX = 16 * nblk;
+
+  uint8_t* reg = (uint8_t*)smem;
+  int32_t* nq = (int32_t*)(smem + (size_t)(S + 16) * 64);
+  uint32_t* keys = (uint32_t*)(nq + (size_t)(S + 9) * 48);
+  int32_t* rs = (int32_t*)keys;
+
+  // int8 region (luminance - 128); columns beyond the image read as 0
+  for (int i = tid; i < RR * 64; i += blockDim.x) {
+    int y = i >> 6, x = i & 63;
+    int gx = g.ux0 + x;
+    reg[i] = gx < w ? (uint8_t)(d.lum8[(size_t)(g.uy0 + y) * w + gx] ^ 0x80u) : (uint8_t)0;
+  }
+  __syncthreads();
+  // |q|^2 of every union candidate: 8-wide row sums, then 8-tall column sums
+  for (int i = tid; i < RR * NX; i += blockDim.x) {
+    int y = i / NX, x = i - y * NX, s = 0;
+    for (int v = 0; v < kP; v++) {
+      int e = (int8_t)reg[y * 64 + x + v];
+      s += e * e;
+    }
+    rs[y * 48 + x] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < g.ny * NX; i += blockDim.x) {
+    int y = i / NX, x = i - y * NX, s = 0;
+    for (int u = 0; u < kP; u++) s += rs[(y + u) * 48 + x];
+    nq[y * 48 + x] = s;
+  }
+  __syncthreads();
+
+  // A operand: reference m = col, patch rows 2q and 2q+1 (16 bytes)
+  i32x4 A = {0, 0, 0, 0};
+  {
+    int a = col >> 2, b = col & 3;
+    if (a < g.nri && b < g.nci) {
+      int ry = ref_pos(g.ri0 + a, h) - g.uy0, rx = ref_pos(g.ci0 + b, w) - g.ux0;
+      uint64_t r0 = lds_bytes8(reg, (ry + 2 * q) * 64 + rx);
+      uint64_t r1 = lds_bytes8(reg, (ry + 2 * q + 1) * 64 + rx);
+      A[0] = (int)(uint32_t)r0;
+      A[1] = (int)(uint32_t)(r0 >> 32);
+      A[2] = (int)(uint32_t)r1;
+      A[3] = (int)(uint32_t)(r1 >> 32);
+    }
+  }
+  // accumulator rows 4q+v are references (row q, column v) of the block
+  int mwy[4], mwx[4], mry[4], mrx[4], mnp[4];
+  bool mval[4];
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    mval[v] = q < g.nri && v < g.nci;
+    int ry = ref_pos(g.ri0 + (q < g.nri ? q : 0), h), rx = ref_pos(g.ci0 + (v < g.nci ? v : 0), w);
+    int wy, wx, t0;
+    window_1d(ry, h, S, wy, t0);
+    window_1d(rx, w, S, wx, t0);
+    mwy[v] = wy - g.uy0;
+    mwx[v] = wx - g.ux0;
+    mry[v] = ry - g.uy0;
+    mrx[v] = rx - g.ux0;
+    mnp[v] = nq[mry[v] * 48 + mrx[v]];
+  }
+  const uint32_t thr = d.thr1;
+  const int ntile = g.ny * nblk;
+  for (int p = wave; p < ntile; p += nwaves) {
+    int cy = p / nblk, blk = p - cy * nblk;
+    int cx = 16 * blk + col;
+    uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * 64 + cx);
+    uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * 64 + cx);
+    i32x4 B;
+    B[0] = (int)(uint32_t)r0;
+    B[1] = (int)(uint32_t)(r0 >> 32);
+    B[2] = (int)(uint32_t)r1;
+    B[3] = (int)(uint32_t)(r1 >> 32);
+    i32x4 D = {0, 0, 0, 0};
+    D = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, D, 0, 0, 0);
+    int nqc = nq[cy * 48 + cx];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      int wyy = cy - mwy[v], wxx = cx - mwx[v];
+      if (mval[v] && (unsigned)wyy < (unsigned)SH && (unsigned)wxx < (unsigned)SW) {
+        int dd = mnp[v] + nqc - 2 * D[v];
+        bool isref = cy == mry[v] && cx == mrx[v];
+        uint32_t key = (!isref && (uint32_t)dd <= thr) ? (((uint32_t)dd << 10) | (uint32_t)(wyy * SW + wxx))
+                                                       : kNone32;
+        keys[(4 * q + v) * SS + wyy * SW + wxx] = key;
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int m = wave; m < 16; m += nwaves) {
+    int a = m >> 2, b = m & 3;
+    if (a >= g.nri || b >= g.nci) continue;
+    uint32_t k[16];
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+      int i = l + 64 * t;
+      k[t] = i < SS ? keys[m * SS + i] : kNone32;
+    }
+    uint32_t sel;
+    int n = select_group<uint32_t>(k, nmax, keys + m * SS, sel);
+    int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
+    window_1d(ry, h, S, wy, t0);
+    window_1d(rx, w, S, wx, t0);
+    size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
+    int32_t* o = d.idx1 + r * nmax;
+    if (l == 0) {
+      o[0] = ry * w + rx;
+      d.cnt1[r] = n;
+    }
+    if (l + 1 < nmax) {
+      int gi = -1;
+      if (l < n - 1) {
+        int widx = (int)(sel & 1023u);
+        gi = (wy + widx / SW) * w + wx + widx % SW;
+      }
+      o[l + 1] = gi;
+    }
+  }
+}
+
+// =========================================================== step-2 match ==
+// LDS: FP32 luminance region [(S+16)][49], per-wave selection scratch.
+constexpr int kM2Pitch = 49;
+__host__ __device__ inline size_t match2_lds_bytes(int S, int nwaves) {
+  size_t regb = ((size_t)(S + 16) * kM2Pitch * 4 + 15) & ~(size_t)15;
+  return regb + (size_t)nwaves * S * S * 8;
+}
+
+__device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
+  const int S = kp.S2, nmax = kp.n2;
+  const int h = d.h, w = d.w;
+  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
+  const int SH = g.SH, SW = g.SW, SS = SH * SW;
+  const int RR = g.ny + 7;
+  float* reg = (float*)smem;
+  uint64_t* bufs = (uint64_t*)(smem + (((size_t)(S + 16) * kM2Pitch * 4 + 15) & ~(size_t)15));
+
+  for (int i = tid; i < RR * kM2Pitch; i += blockDim.x) {
+    int y = i / kM2Pitch, x = i - y * kM2Pitch;
+    int gx = g.ux0 + x;
+    reg[i] = gx < w ? d.lumf[(size_t)(g.uy0 + y) * w + gx] : 0.f;
+  }
+  __syncthreads();
+
+  const int wyy = l >> 1, wxx0 = (l & 1) * 16;
+  const bool lane_ok = wyy < SH && wxx0 < SW;
+  const float thr = d.thr2;
+  for (int m = wave; m < 16; m += nwaves) {
+    int a = m >> 2, b = m & 3;
+    if (a >= g.nri || b >= g.nci) continue;
+    int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
+    window_1d(ry, h, S, wy, t0);
+    window_1d(rx, w, S, wx, t0);
+    const int ryr = ry - g.uy0, rxr = rx - g.ux0, wyr = wy - g.uy0, wxr = wx - g.ux0;
+    float acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) acc[c] = 0.f;
+    for (int u = 0; u < kP; u++) {
+      float P[8], rw[23];
+#pragma unroll
+      for (int v = 0; v < 8; v++) P[v] = reg[(ryr + u) * kM2Pitch + rxr + v];
+      if (lane_ok) {
+        const float* src = reg + (wyr + wyy + u) * kM2Pitch + wxr + wxx0;
+#pragma unroll
+        for (int i = 0; i < 23; i++) rw[i] = src[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 23; i++) rw[i] = 0.f;
+      }
+#pragma unroll
+      for (int c = 0; c < 16; c++) {
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+          float e = P[v] - rw[c + v];
+          acc[c] = __builtin_fmaf(e, e, acc[c]);
+        }
+      }
+    }
+    uint64_t k[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) {
+      int wxx = wxx0 + c;
+      bool isref = (wyr + wyy == ryr) && (wxr + wxx == rxr);
+      bool ok = lane_ok && wxx < SW && !isref && acc[c] <= thr;
+      k[c] = ok ? (((uint64_t)__float_as_uint(acc[c]) << 32) | (uint64_t)(wyy * SW + wxx)) : kNone64;
+    }
+    uint64_t sel;
+    int n = select_group<uint64_t>(k, nmax, bufs + (size_t)wave * SS, sel);
+    size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
+    int32_t* o = d.idx2 + r * nmax;
+    if (l == 0) {
+      o[0] = ry * w + rx;
+      d.cnt2[r] = n;
+    }
+    if (l + 1 < nmax) {
+      int gi = -1;
+      if (l < n - 1) {
+        int widx = (int)(sel & 1023u);
+        gi = (wy + widx / SW) * w + wx + widx % SW;
+      }
+      o[l + 1] = gi;
+    }
+  }
+}
+// ========================================================= collaborative ==
+// Each wave filters the groups of its own T x T tile of references and
+// aggregates them into a wave-private LDS accumulator covering the tile's
+// search region; the region is then added into num/den with one coalesced
+// atomic per touched pixel.  A workgroup only shares the transform tables.
+//
+// Per group (n members, one channel), with the 16x16 fragments of
+// bm3d_device.h (g = member, t = Hadamard index, pix = 8x8 pixel, coef = 8x8
+// DCT coefficient, CC[coef][pix] = C[a][u] C[b][v]):
+//   D1[g][coef]   = sum_pix G^T[g][pix]  CC^T[pix][coef]   2-D DCT
+//   D2[t][coef]   = sum_g   H[t][g]      D1[g][coef]        WHT (+-1, /sqrt n)
+//   shrink D2 (hard threshold / Wiener)
+//   D3[coef][g]   = sum_t   D2'^T[coef][t] H[t][g]          inverse WHT
+//   D4[pix][g]    = sum_coef CC^T[pix][coef] D3[coef][g]     inverse 2-D DCT
+// Each product's accumulator feeds the next one without data movement.
+//
+// Aggregation without atomics.  Within a wave, accumulator pixel (y, x) is
+// only ever updated by lane (y mod 8)*8 + (x mod 8): an 8x8 member patch
+// covers every residue exactly once, so one 64-lane step adds a whole member
+// at 64 distinct addresses, and all contributions to one pixel come from one
+// lane in program order.  Filtered patches reach their owning lanes through a
+// small per-wave staging buffer, four members per step (coinciding addresses
+// within a step are merged in registers).  The denominator sum of w K(u)K(v)
+// over member placements equals the Kaiser window correlated with the
+// per-position sum of group weights, so only one add per member is made (the
+// weight map W) and den is formed at flush time.
+template <class XF> struct FilterCfg {
+  typedef typename XF::frag frag;
+  static constexpr int kWaves = sizeof(frag) == 16 ? 4 : 6;  // waves per workgroup
+  static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag) + 64 * 4; }
+  static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
+  // row pitch of the numerator region: = 8 (mod 16) so the 8 rows of a
+  // member patch fall in different LDS banks
+  static __host__ __device__ int pitch(int rw) { return rw + ((24 - rw % 16) % 16); }
+  static __host__ __device__ int rw(int S, int T) { return 3 * (T - 1) + S; }
+  static __host__ __device__ size_t per_wave(int S, int T) {
+    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + (size_t)rw(S, T) * rw(S, T) + 16 * 64) * 4;
+  }
+  static __host__ __device__ size_t bytes(int S, int T) { return tables() + kWaves * per_wave(S, T); }
+};
+
+__host__ __device__ inline size_t filter_lds_bytes(int xform, int S, int T) {
+  return xform == 0 ? FilterCfg<XF32>::bytes(S, T) : FilterCfg<XBF16>::bytes(S, T);
+}
+__host__ __device__ inline int filter_waves(int xform) {
+  return xform == 0 ? FilterCfg<XF32>::kWaves : FilterCfg<XBF16>::kWaves;
+}
+
+// Hadamard entry (+-1) of the n-point Sylvester matrix, 0 outside n x n.
+__device__ inline float had(int t, int g, int n) {
+  return (t < n && g < n) ? ((__popc(t & g) & 1) ? -1.f : 1.f) : 0.f;
+}
+
+template <class XF>
+__device__ inline typename XF::frag had_frag(int rt, int kt, int n) {
+  // A-operand layout: row 16*rt + l%16, contraction 16*kt + 4*(l/16) + v
+  const int l = lane_id();
+  const int row = 16 * rt + (l & 15), k0 = 16 * kt + 4 * (l >> 4);
+  f32x4 a;
+  a[0] = had(row, k0, n);
+  a[1] = had(row, k0 + 1, n);
+  a[2] = had(row, k0 + 2, n);
+  a[3] = had(row, k0 + 3, n);
+  return XF::cvt(a);
+}
+
+// Builds the two DCT fragment tables of a workgroup (caller synchronises).
+template <class XF>
+__device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, float* Cm) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    int a = tid >> 3, u = tid & 7;
+    double s = a == 0 ? 0.35355339059327376 : 0.5;
+    Cm[tid] = (float)(s * cos(3.14159265358979323846 * (2 * u + 1) * a / 16.0));
+  }
+  __syncthreads();
+  for (int i = tid; i < 2 * 16 * 64; i += blockDim.x) {
+    int tab = i >> 10, f = (i >> 6) & 15, ln = i & 63;
+    int lq = ln >> 4, lc = ln & 15;
+    f32x4 v4;
+    for (int v = 0; v < 4; v++) {
+      int pix, coef;
+      if (tab == 0) {  // f = kt*4 + nt: B[k=pix][j=coef]
+        pix = 16 * (f >> 2) + 4 * lq + v;
+        coef = 16 * (f & 3) + lc;
+      } else {  // f = mt*4 + ct: A[i=pix][k=coef]
+        pix = 16 * (f >> 2) + lc;
+        coef = 16 * (f & 3) + 4 * lq + v;
+      }
+      v4[v] = Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
+    }
+    (tab == 0 ? tabB : tabA)[f * 64 + ln] = XF::cvt(v4);
+  }
+}
+
+template <int STEP, class XF>
+__device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
+                                 const typename XF::frag* __restrict__ tabB,
+                                 const typename XF::frag* __restrict__ tabA, float* wnum, float* wW) {
+  typedef typename XF::frag frag;
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
+  const int nmax = STEP == 1 ? kp.n1 : kp.n2;
+  const int32_t* __restrict__ idx = STEP == 1 ? d.idx1 : d.idx2;
+  const int32_t* __restrict__ cnt = STEP == 1 ? d.cnt1 : d.cnt2;
+  const int T = kp.tile;
+  const int h = d.h, w = d.w;
+  const size_t hw = (size_t)h * w;
+  const int l = lane_id();
+  const int q = l >> 4, col = l & 15;
+  const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, T, ty, tx);
+  const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
+  const int RP = FilterCfg<XF>::pitch(RW);  // its row pitch
+  const int WW = g.nx;                      // weight map row pitch (positions)
+  float* wst = wW + FilterCfg<XF>::rw(S, T) * FilterCfg<XF>::rw(S, T);  // staging [16][64]
+
+  for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
+  for (int i = l; i < g.ny * WW; i += 64) wW[i] = 0.f;
+  wave_lds_sync();
+
+  const float centre = channel_centre(d.c, ch);
+  const float* __restrict__ noisy = d.planar + ch * hw;
+  const float* __restrict__ basic = d.basic + ch * hw;
+  const float sig2 = d.sigma * d.sigma;
+  const float thr = d.lam_sigma;
+  float Ku[4], Kv[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    Ku[i] = kp.kaiser[2 * i + (q >> 1)];
+    Kv[i] = kp.kaiser[4 * (q & 1) + i];
+  }
+
+  const int nrefs = g.nri * g.nci;
+  for (int j = 0; j < nrefs; j++) {
+    const int ri = g.ri0 + j / g.nci, ci = g.ci0 + j % g.nci;
+    const size_t r = (size_t)ri * d.nc + ci;
+    const int n = min(max(cnt[r], 1), nmax);
+    const int NG = n > 16 ? 2 : 1;
+    const float rsn = n == 1 ? 1.f : n == 2 ? 0.70710678118654752f : n == 4 ? 0.5f
+                    : n == 8 ? 0.35355339059327376f : n == 16 ? 0.25f : 0.17677669529663688f;
+    int my[2], mx[2];
+    bool mv[2];
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      int gm = 16 * gt + col;
+      mv[gt] = gt < NG && gm < n;
+      int gi = idx[r * nmax + (mv[gt] ? gm : 0)];
+      int yy = gi >= 0 ? gi / w : -1, xx = gi >= 0 ? gi - yy * w : -1;
+      // a member must lie in the tile's search region (true for any grouping
+      // made with the same window rule); anything else is ignored
+      bool inside = yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
+      mv[gt] = mv[gt] && inside;
+      my[gt] = inside ? yy : g.uy0;
+      mx[gt] = inside ? xx : g.ux0;
+    }
+
+    // ---- forward: 2-D DCT then WHT (noisy; and basic in step 2)
+    f32x4 D2[2][4], D2b[2][4];
+    {
+      f32x4 D1[2][4];
+#pragma unroll
+      for (int gt = 0; gt < 2; gt++) {
+        if (gt >= NG) break;
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
+#pragma unroll
+        for (int kt = 0; kt < 4; kt++) {
+          const float* src = noisy + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+          f32x4 a;
+#pragma unroll
+          for (int v = 0; v < 4; v++) a[v] = mv[gt] ? src[v] - centre : 0.f;
+          frag af = XF::cvt(a);
+#pragma unroll
+          for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < 2; tt++) {
+        if (tt >= NG) break;
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++) {
+          f32x4 acc = zero4();
+#pragma unroll
+          for (int gt = 0; gt < 2; gt++) {
+            if (gt >= NG) break;
+            acc = XF::mma(had_frag<XF>(tt, gt, n), XF::cvt(D1[gt][nt]), acc);
+          }
+          D2[tt][nt] = acc * rsn;
+        }
+      }
+      if (STEP == 2) {
+#pragma unroll
+        for (int gt = 0; gt < 2; gt++) {
+          if (gt >= NG) break;
+#pragma unroll
+          for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
+#pragma unroll
+          for (int kt = 0; kt < 4; kt++) {
+            const float* src = basic + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+            f32x4 a;
+#pragma unroll
+            for (int v = 0; v < 4; v++) a[v] = mv[gt] ? src[v] - centre : 0.f;
+            frag af = XF::cvt(a);
+#pragma unroll
+            for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
+          }
+        }
+#pragma unroll
+        for (int tt = 0; tt < 2; tt++) {
+          if (tt >= NG) break;
+#pragma unroll
+          for (int nt = 0; nt < 4; nt++) {
+            f32x4 acc = zero4();
+#pragma unroll
+            for (int gt = 0; gt < 2; gt++) {
+              if (gt >= NG) break;
+              acc = XF::mma(had_frag<XF>(tt, gt, n), XF::cvt(D1[gt][nt]), acc);
+            }
+            D2b[tt][nt] = acc * rsn;
+          }
+        }
+      }
+    }
+
+    // ---- shrinkage; the centre only moves the 3-D DC, restored here
+    const float off = 8.f * centre * sqrtf((float)n);
+    float wgt;
+    {
+      float stat = 0.f;
+#pragma unroll
+      for (int tt = 0; tt < 2; tt++) {
+        if (tt >= NG) break;
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++) {
+#pragma unroll
+          for (int v = 0; v < 4; v++) {
+            const int t = 16 * tt + 4 * q + v;
+            const bool valid = t < n;
+            const bool isdc = tt == 0 && nt == 0 && l == 0 && v == 0;
+            float s = D2[tt][nt][v] + (isdc ? off : 0.f);
+            float o;
+            if (STEP == 1) {
+              bool keep = valid && fabsf(s) > thr;
+              stat += keep ? 1.f : 0.f;
+              o = keep ? s : 0.f;
+            } else {
+              float sb = D2b[tt][nt][v] + (isdc ? off : 0.f);
+              float b2 = sb * sb;
+              float dd = b2 + sig2;
+              float W = dd > 0.f ? b2 / dd : 1.f;
+              W = valid ? W : 0.f;
+              stat += W * W;
+              o = W * s;
+            }
+            D2[tt][nt][v] = isdc ? o - off : o;
+          }
+        }
+      }
+      stat = wave_sum_f(stat);
+      if (STEP == 1 && d.nkept && l == 0) d.nkept[(size_t)ch * d.nr * d.nc + r] = (int32_t)stat;
+      wgt = STEP == 1 ? (stat >= 1.f ? 1.f / stat : 1.f) : (stat > 0.f ? 1.f / stat : 1.f);
+    }
+
+    // ---- inverse WHT
+    f32x4 D3[4][2];
+#pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+#pragma unroll
+      for (int gt = 0; gt < 2; gt++) {
+        if (gt >= NG) break;
+        f32x4 acc = zero4();
+#pragma unroll
+        for (int tt = 0; tt < 2; tt++) {
+          if (tt >= NG) break;
+          acc = XF::mma(XF::cvt(D2[tt][ct]), had_frag<XF>(gt, tt, n), acc);
+        }
+        D3[ct][gt] = acc * rsn;
+      }
+    }
+    // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
+    const int ru = l >> 3, rv = l & 7;
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      if (gt >= NG) break;
+      frag b3[4];
+#pragma unroll
+      for (int ct = 0; ct < 4; ct++) b3[ct] = XF::cvt(D3[ct][gt]);
+#pragma unroll
+      for (int mt = 0; mt < 4; mt++) {
+        f32x4 acc = zero4();
+#pragma unroll
+        for (int ct = 0; ct < 4; ct++) acc = XF::mma(tabA[(mt * 4 + ct) * 64 + l], b3[ct], acc);
+        f32x4 add;
+#pragma unroll
+        for (int v = 0; v < 4; v++) add[v] = wgt * Ku[mt] * Kv[v] * (acc[v] + centre);
+        *(f32x4*)(wst + col * 64 + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
+      }
+      if (q == 0 && mv[gt]) {
+        float* pw = wW + (my[gt] - g.uy0) * WW + (mx[gt] - g.ux0);
+        *pw = *pw + wgt;
+      }
+      wave_lds_sync();
+      const int packed = mv[gt] ? (((my[gt] - g.uy0) << 16) | (mx[gt] - g.ux0)) : -1;
+      for (int mb = 0; mb < 16; mb += 4) {
+        if (16 * gt + mb >= n) break;
+        int a[4];
+        float sv[4], o[4];
+        bool ok[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int pk = __builtin_amdgcn_readlane(packed, mb + i);
+          ok[i] = pk >= 0;
+          const int py = pk >> 16, px = pk & 0xffff;
+          const int u = (ru - py) & 7, v = (rv - px) & 7;
+          a[i] = ok[i] ? (py + u) * RP + px + v : 0;
+          sv[i] = ok[i] ? wst[(mb + i) * 64 + u * 8 + v] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) o[i] = ok[i] ? wnum[a[i]] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          float t = o[i] + sv[i];
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            if (j != i && ok[j] && a[j] == a[i]) t += sv[j];
+          if (ok[i]) wnum[a[i]] = t;
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+
+  // ---- flush: num as accumulated; den = weight map (x) Kaiser window
+  float* gnum = d.num + ch * hw;
+  float* gden = d.den + ch * hw;
+  for (int i = l; i < RH * RW; i += 64) {
+    int y = i / RW, x = i - y * RW;
+    float nv = wnum[y * RP + x];
+    float dv = 0.f;
+    for (int u = 0; u < 8; u++) {
+      int py = y - u;
+      if (py < 0 || py >= g.ny) continue;
+      float rowsum = 0.f;
+      for (int v = 0; v < 8; v++) {
+        int px = x - v;
+        if (px >= 0 && px < g.nx) rowsum += kp.kaiser[v] * wW[py * WW + px];
+      }
+      dv += kp.kaiser[u] * rowsum;
+    }
+    if (dv != 0.f) {
+      size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
+      atomicAdd(gnum + o, nv);
+      atomicAdd(gden + o, dv);
+    }
+  }
+  wave_lds_sync();
+}
+
+// One workgroup = kWaves waves, each on its own reference tile.
+template <int STEP, class XF>
+__device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch, char* smem) {
+  typedef typename XF::frag frag;
+  typedef FilterCfg<XF> C;
+  frag* tabB = (frag*)smem;
+  frag* tabA = tabB + 16 * 64;
+  float* Cm = (float*)(tabA + 16 * 64);
+  filter_tables<XF>(tabB, tabA, Cm);
+  __syncthreads();
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
+  const int wave = threadIdx.x >> 6;
+  float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
+  float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
+  const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
+  const int t = blockIdx.x * C::kWaves + wave;
+  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wnum, wW);
+}
+
+template <int STEP, class XF>
+__device__ void filter_block_batch(const ImgDesc* ds, const KParams& kp, const Work* wk, int nw, char* smem) {
+  typedef typename XF::frag frag;
+  typedef FilterCfg<XF> C;
+  frag* tabB = (frag*)smem;
+  frag* tabA = tabB + 16 * 64;
+  float* Cm = (float*)(tabA + 16 * 64);
+  filter_tables<XF>(tabB, tabA, Cm);
+  __syncthreads();
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
+  const int wave = threadIdx.x >> 6;
+  float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
+  float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
+  for (int i = blockIdx.x * C::kWaves + wave; i < nw; i += gridDim.x * C::kWaves) {
+    const Work it = wk[i];
+    filter_wave_tile<STEP, XF>(ds[it.img], kp, it.y, it.x, it.ch, tabB, tabA, wnum, wW);
+  }
+}
+
+// ================================================================ kernels ==
+__global__ void __launch_bounds__(kThreads) k_prep(ImgDesc d) { prep_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_fill(ImgDesc d) { fill_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_agg1(ImgDesc d) { agg1_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_agg2(ImgDesc d) { agg2_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_lum(ImgDesc d) { lum_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_match1(ImgDesc d, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  match1_block(d, kp, blockIdx.y, blockIdx.x, smem);
+}
+__global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  match2_block(d, kp, blockIdx.y, blockIdx.x, smem);
+}
+template <int STEP, class XF>
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) k_filter(ImgDesc d, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
+}
+
+// batched: walk the work list
+__global__ void __launch_bounds__(kThreads) kb_elem(int stage, const ImgDesc* ds, const Work* wk, int nw) {
+  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+    const Work it = wk[i];
+    const ImgDesc& d = ds[it.img];
+    if (stage == STAGE_PREP) {
+      prep_chunk(d, it.y);
+    } else if (stage == STAGE_AGG1) {
+      agg1_chunk(d, it.y);
+    } else {
+      agg2_chunk(d, it.y);
+    }
+  }
+}
+__global__ void __launch_bounds__(kThreads) kb_fill(const ImgDesc* ds, const Work* wk, int nw) {
+  for (int i = blockIdx.x; i < nw; i += gridDim.x) fill_chunk(ds[wk[i].img], wk[i].y);
+}
+__global__ void __launch_bounds__(kThreads) kb_match1(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
+  extern __shared__ __align__(16) char smem[];
+  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+    const Work it = wk[i];
+    match1_block(ds[it.img], kp, it.y, it.x, smem);
+    __syncthreads();
+  }
+}
+__global__ void __launch_bounds__(kThreads) kb_match2(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
+  extern __shared__ __align__(16) char smem[];
+  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
+    const Work it = wk[i];
+    match2_block(ds[it.img], kp, it.y, it.x, smem);
+    __syncthreads();
+  }
+}
+template <int STEP, class XF>
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) kb_filter(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
+  extern __shared__ __align__(16) char smem[];
+  filter_block_batch<STEP, XF>(ds, kp, wk, nw, smem);
+}
+
+// ============================================================ launchers ==
+static int post(hipStream_t s, bool sync) {
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && sync) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? 0 : -1;
+}
+
+static int elem_blocks(const ImgDesc& d, bool planes) {
+  size_t n = (size_t)d.h * d.w * (planes ? d.c : 1);
+  return (int)((n + kChunk - 1) / kChunk);
+}
+
+template <class F> static void lds_attr(F f, size_t bytes) {
+  (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s, bool sync) {
+  switch (stage) {
+    case STAGE_PREP:
+      hipLaunchKernelGGL(k_prep, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      break;
+    case STAGE_FILL:
+      hipLaunchKernelGGL(k_fill, dim3(elem_blocks(d, true)), dim3(kThreads), 0, s, d);
+      break;
+    case STAGE_AGG1:
+      hipLaunchKernelGGL(k_agg1, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      break;
+    case STAGE_AGG2:
+      hipLaunchKernelGGL(k_agg2, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      break;
+    case STAGE_LUM:
+      hipLaunchKernelGGL(k_lum, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      break;
+    case STAGE_MATCH1:
+    case STAGE_MATCH2: {
+      dim3 grid((d.nc + 3) / 4, (d.nr + 3) / 4);
+      if (stage == STAGE_MATCH1) {
+        size_t b = match1_lds_bytes(kp.S1);
+        lds_attr(k_match1, b);
+        hipLaunchKernelGGL(k_match1, grid, dim3(kThreads), b, s, d, kp);
+      } else {
+        size_t b = match2_lds_bytes(kp.S2, kThreads / 64);
+        lds_attr(k_match2, b);
+        hipLaunchKernelGGL(k_match2, grid, dim3(kThreads), b, s, d, kp);
+      }
+      break;
+    }
+    case STAGE_FILTER1:
+    case STAGE_FILTER2: {
+      const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
+      const int nw = filter_waves(xform);
+      const int ntiles = ((d.nc + kp.tile - 1) / kp.tile) * ((d.nr + kp.tile - 1) / kp.tile);
+      dim3 grid((ntiles + nw - 1) / nw, d.c);
+      size_t b = filter_lds_bytes(xform, S, kp.tile);
+#define LAUNCH_F(STEP, XF)                                                                \
+  do {                                                                                    \
+    lds_attr(k_filter<STEP, XF>, b);                                                      \
+    hipLaunchKernelGGL((k_filter<STEP, XF>), grid, dim3(64 * nw), b, s, d, kp);          \
+  } while (0)
+      if (stage == STAGE_FILTER1) {
+        if (xform == 0) LAUNCH_F(1, XF32); else if (xform == 1) LAUNCH_F(1, XBF16); else LAUNCH_F(1, XF16);
+      } else {
+        if (xform == 0) LAUNCH_F(2, XF32); else if (xform == 1) LAUNCH_F(2, XBF16); else LAUNCH_F(2, XF16);
+      }
+#undef LAUNCH_F
+      break;
+    }
+    default:
+      return -1;
+  }
+  return post(s, sync);
+}
+
+int launch_batch(int stage, int xform, const ImgDesc* ds, const KParams& kp, const Work* wk, int nw,
+                 int blocks, hipStream_t s, bool sync) {
+  // blocks = 0: one workgroup per work item (per filter_waves() items for the
+  // filters); otherwise a persistent grid of that many workgroups.
+  if (nw <= 0) return 0;
+  int grid = (blocks <= 0 || blocks > nw) ? nw : blocks;
+  switch (stage) {
+    case STAGE_PREP:
+    case STAGE_AGG1:
+    case STAGE_AGG2:
+      hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, ds, wk, nw);
+      break;
+    case STAGE_FILL:
+      hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(kThreads), 0, s, ds, wk, nw);
+      break;
+    case STAGE_MATCH1: {
+      size_t b = match1_lds_bytes(kp.S1);
+      lds_attr(kb_match1, b);
+      hipLaunchKernelGGL(kb_match1, dim3(grid), dim3(kThreads), b, s, ds, kp, wk, nw);
+      break;
+    }
+    case STAGE_MATCH2: {
+      size_t b = match2_lds_bytes(kp.S2, kThreads / 64);
+      lds_attr(kb_match2, b);
+      hipLaunchKernelGGL(kb_match2, dim3(grid), dim3(kThreads), b, s, ds, kp, wk, nw);
+      break;
+    }
+    case STAGE_FILTER1:
+    case STAGE_FILTER2: {
+      // work items are wave tiles; a workgroup runs filter_waves() of them at once
+      const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
+      const int wv = filter_waves(xform);
+      int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
+      size_t b = filter_lds_bytes(xform, S, kp.tile);
+#define LAUNCH_FB(STEP, XF)                                                               \
+  do {                                                                                    \
+    lds_attr(kb_filter<STEP, XF>, b);                                                     \
+    hipLaunchKernelGGL((kb_filter<STEP, XF>), dim3(g), dim3(64 * wv), b, s, ds, kp, wk, nw); \
+  } while (0)
+      if (stage == STAGE_FILTER1) {
+        if (xform == 0) LAUNCH_FB(1, XF32); else if (xform == 1) LAUNCH_FB(1, XBF16); else LAUNCH_FB(1, XF16);
+      } else {
+        if (xform == 0) LAUNCH_FB(2, XF32); else if (xform == 1) LAUNCH_FB(2, XBF16); else LAUNCH_FB(2, XF16);
+      }
+#undef LAUNCH_FB
+      break;
+    }
+    default:
+      return -1;
+  }
+  return post(s, sync);
+}
+
+size_t stage_lds_bytes(int stage, int xform, const KParams& kp) {
+  switch (stage) {
+    case STAGE_MATCH1: return match1_lds_bytes(kp.S1);
+    case STAGE_MATCH2: return match2_lds_bytes(kp.S2, kThreads / 64);
+    case STAGE_FILTER1: return filter_lds_bytes(xform, kp.S1, kp.tile);
+    case STAGE_FILTER2: return filter_lds_bytes(xform, kp.S2, kp.tile);
+    default: return 0;
+  }
+}
+
+int elem_chunk() { return kChunk; }
+int filter_block_waves(int xform) { return filter_waves(xform); }
+
+}  // namespace bm3d
