@@ -63,6 +63,10 @@ typedef enum {
 } bm3d_xform;
 
 #define BM3D_FLAG_DEBUG_SYNC 1u
+/* tau_ht/tau_wie of each image follow its own sigma with the rule of
+ * bm3d_params_default (sigma <= 40: 2500/400, else 5000/3500) instead of the
+ * params' values -- for batches and request streams with mixed noise levels */
+#define BM3D_FLAG_SIGMA_PROFILE 2u
 
 typedef struct {
   int search_ht, search_wie; /* S of each step, 1..32 */
@@ -140,11 +144,13 @@ int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma, const bm3
 
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
- * image's working buffers and the device descriptor tables (allocated at
- * creation).  Input/output pointers can be re-bound between runs without
- * re-planning.  bm3d_batch_run enqueues the whole two-step pass over all
- * images as persistent kernels that walk a tile list; bm3d_batch_capture
- * records it into a HIP graph once and bm3d_batch_launch replays it. */
+ * image's working buffers and a device table of image descriptors with
+ * per-image work counts (allocated at creation).  Input/output pointers can
+ * be re-bound between runs without re-planning.  bm3d_batch_run enqueues
+ * the whole two-step pass over all images, one launch per stage whose
+ * workgroups (a persistent grid if params->persistent_wgs > 0) decode their
+ * (image, tile) from the table; bm3d_batch_capture records it into a HIP
+ * graph once and bm3d_batch_launch replays it. */
 typedef struct {
   const uint8_t* img; /* device HWC uint8 */
   float* out;         /* device HWC float */
@@ -170,6 +176,33 @@ int bm3d_batch_launch(bm3d_batch* plan, bm3d_stream_t stream);
 int bm3d_batch_run_stages(bm3d_batch* plan, int i0, int i1, int first, int last,
                           bm3d_stream_t stream);
 int bm3d_batch_destroy(bm3d_batch* plan);
+
+/* ---- serving: stage-level continuous batching ----
+ * A server advances a changing set of in-flight requests one stage per
+ * tick.  Each request brings its device buffers (input, output and a
+ * workspace of bm3d_workspace_size bytes, which keeps its planar channels,
+ * basic estimate, aggregation buffers and groups between ticks); all
+ * requests at the same stage in a tick share one batched launch.  A request
+ * enters at stage 0 and is complete once the tick that ran its stage 6 has
+ * finished on the stream.  Ticks are asynchronous; the server allocates only
+ * at creation (two small descriptor tables, device and pinned host). */
+typedef struct bm3d_server bm3d_server;
+
+typedef struct {
+  const uint8_t* img; /* device HWC uint8 */
+  float* out;         /* device HWC float */
+  int h, w, c;
+  float sigma;
+  void* workspace;    /* device, >= bm3d_workspace_size(h, w, c, p) bytes */
+  size_t workspace_bytes;
+  int stage;          /* stage to run in this tick: 0..6 as in bm3d_batch_run_stages, -1 = none */
+} bm3d_request;
+
+int bm3d_server_create(int max_requests, const bm3d_params* p, bm3d_server** server);
+/* reqs: host array of n (<= max_requests) requests; the request data may
+ * change freely between ticks (the table is copied at call time). */
+int bm3d_server_tick(bm3d_server* server, const bm3d_request* reqs, int n, bm3d_stream_t stream);
+int bm3d_server_destroy(bm3d_server* server);
 
 /* Measures the candidate filter tile shapes / persistent grid sizes on the
  * current device for these params and writes the fastest into p

@@ -21,6 +21,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 XF_FP32, XF_BF16, XF_FP16 = 0, 1, 2
 FLAG_DEBUG_SYNC = 1
+FLAG_SIGMA_PROFILE = 2
 STAGES = ("prep", "match1", "filter1", "agg1", "match2", "filter2", "agg2")
 
 
@@ -45,6 +46,13 @@ class ImageDesc(ctypes.Structure):
                 ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
+                ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("stage", ctypes.c_int)]
+
+
 _vp, _i, _f, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
 _PP = ctypes.POINTER(Params)
 _SIGS = {
@@ -66,6 +74,9 @@ _SIGS = {
     "bm3d_batch_run_stages": (_i, [_vp, _i, _i, _i, _i, _vp]),
     "bm3d_batch_destroy": (_i, [_vp]),
     "bm3d_autotune": (_i, [_PP, ctypes.c_char_p]),
+    "bm3d_server_create": (_i, [_i, _PP, ctypes.POINTER(_vp)]),
+    "bm3d_server_tick": (_i, [_vp, ctypes.POINTER(Request), _i, _vp]),
+    "bm3d_server_destroy": (_i, [_vp]),
     "bm3d_strerror": (ctypes.c_char_p, [_i]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -247,6 +258,33 @@ class Batch:
     def close(self):
         if self._h:
             _lib.bm3d_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Stage-level continuous batching on the device (bm3d_server_*)."""
+
+    def __init__(self, max_requests: int, p: Params):
+        self.max_requests = max_requests
+        self._h = ctypes.c_void_p()
+        _check(_lib.bm3d_server_create(max_requests, ctypes.byref(p), ctypes.byref(self._h)),
+               "bm3d_server_create")
+
+    def tick(self, requests, stream=None):
+        """requests: list of Request structures (stage set per request)."""
+        arr = (Request * max(1, len(requests)))(*requests)
+        _check(_lib.bm3d_server_tick(self._h, arr, len(requests), _stream(stream)),
+               "bm3d_server_tick")
+
+    def close(self):
+        if self._h:
+            _lib.bm3d_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

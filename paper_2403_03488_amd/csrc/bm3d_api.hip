@@ -96,10 +96,15 @@ ImgDesc base_desc(int h, int w, int c, float sigma, const bm3d_params* p) {
   d.sigma = sigma;
   d.lam_sigma = p ? p->lambda_ht * sigma : 0.f;
   if (p) {
-    double t1 = 64.0 * (double)p->tau_ht;
+    float tau1 = p->tau_ht, tau2 = p->tau_wie;
+    if (p->flags & BM3D_FLAG_SIGMA_PROFILE) {
+      tau1 = sigma > 40.f ? 5000.f : 2500.f;
+      tau2 = sigma > 40.f ? 3500.f : 400.f;
+    }
+    double t1 = 64.0 * (double)tau1;
     double cap = (double)((1u << 22) - 1);
     d.thr1 = (uint32_t)(t1 >= cap ? cap : floor(t1));
-    d.thr2 = 64.0f * p->tau_wie;
+    d.thr2 = 64.0f * tau2;
   }
   return d;
 }
@@ -304,14 +309,9 @@ extern "C" int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma
 }
 
 // ============================================================ batched plans
-// Each stage walks a device work list sorted by image; the per-image offsets
-// let a sub-range of images advance through a sub-range of stages (the unit
-// of stage-level continuous batching).
-namespace {
-constexpr int kNumLists = 4;  // elementwise(pixels), elementwise(planes), match blocks, filter tiles
-enum { WL_PIX = 0, WL_PLANE = 1, WL_MATCH = 2, WL_FILTER = 3 };
-}  // namespace
-
+// A plan holds every image's workspace, the device descriptor table and,
+// for each list kind, the per-image prefix item counts.  A stage over images
+// [i0, i1) is one launch over the item range [prefix[i0], prefix[i1]).
 struct bm3d_batch {
   int n = 0;
   bm3d_params p;
@@ -319,11 +319,10 @@ struct bm3d_batch {
   std::vector<bm3d_image_desc> imgs;
   std::vector<ImgDesc> hd;
   ImgDesc* dd = nullptr;
+  int* dprefix[LIST_KINDS] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> hprefix[LIST_KINDS];
   char* ws = nullptr;
   size_t ws_bytes = 0;
-  std::vector<Work> hw[kNumLists];
-  std::vector<int> off[kNumLists];  // off[list][i] = first item of image i (size n+1)
-  Work* dw[kNumLists] = {nullptr, nullptr, nullptr, nullptr};
   int cus = 256;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -333,26 +332,29 @@ namespace {
 
 __global__ void k_set_desc(ImgDesc* dst, ImgDesc v) { *dst = v; }
 
-int list_of(int stage) {
-  switch (stage) {
-    case STAGE_PREP: case STAGE_AGG1: case STAGE_AGG2: case STAGE_LUM: return WL_PIX;
-    case STAGE_FILL: return WL_PLANE;
-    case STAGE_MATCH1: case STAGE_MATCH2: return WL_MATCH;
-    default: return WL_FILTER;
+int device_cus() {
+  int dev = 0, cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    cus = prop.multiProcessorCount;
+  return cus;
+}
+
+int persistent_blocks(const bm3d_params& p, int cus) {
+  return p.persistent_wgs <= 0 ? 0 : p.persistent_wgs * cus;
+}
+
+void fill_prefix(const ImgDesc* d, int n, const KParams& kp, std::vector<int>* pre) {
+  for (int L = 0; L < LIST_KINDS; L++) {
+    pre[L].assign(n + 1, 0);
+    for (int i = 0; i < n; i++) pre[L][i + 1] = pre[L][i] + items_of(L, d[i], kp.tile, elem_chunk());
   }
 }
 
-int batch_grid(const bm3d_batch* b, int nitems) {
-  (void)nitems;
-  return b->p.persistent_wgs <= 0 ? 0 : b->p.persistent_wgs * b->cus;
-}
-
 int batch_stage(bm3d_batch* b, int stage, int i0, int i1, hipStream_t s) {
-  int L = list_of(stage);
-  int a = b->off[L][i0], e = b->off[L][i1];
-  if (e <= a) return BM3D_OK;
-  int r = launch_batch(stage, b->p.xform, b->dd, b->kp, b->dw[L] + a, e - a, batch_grid(b, e - a), s,
-                       want_sync(&b->p));
+  const int L = list_of_stage(stage);
+  BatchRef br{b->dd, b->dprefix[L], b->n, b->hprefix[L][i0], b->hprefix[L][i1]};
+  int r = launch_batch(stage, b->p.xform, br, b->kp, persistent_blocks(b->p, b->cus), s, want_sync(&b->p));
   return r == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
 
@@ -366,19 +368,17 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
   for (int i = 0; i < n; i++) {
     if ((e = check_image(imgs[i].h, imgs[i].w, imgs[i].c))) return e;
     if ((e = check_sigma(imgs[i].sigma))) return e;
+    if (!imgs[i].img || !imgs[i].out) return BM3D_ERR_ARG;
   }
   bm3d_batch* b = new bm3d_batch();
   b->n = n;
   b->p = *p;
   b->p.workspace = nullptr;
   b->p.workspace_bytes = 0;
+  b->p.debug_nkept = nullptr;
   b->kp = make_kparams(p);
   b->imgs.assign(imgs, imgs + n);
-  int dev = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    b->cus = prop.multiProcessorCount;
-  // workspace for all images
+  b->cus = device_cus();
   std::vector<Layout> Ls(n);
   std::vector<size_t> base(n);
   size_t tot = 0;
@@ -386,55 +386,27 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
     Ls[i] = layout(imgs[i].h, imgs[i].w, imgs[i].c, p);
     base[i] = tot;
     tot += Ls[i].total;
-  }
-  const int chunk = elem_chunk();
-  for (int L = 0; L < kNumLists; L++) b->off[L].assign(n + 1, 0);
-  for (int i = 0; i < n; i++) {
-    const bm3d_image_desc& im = imgs[i];
-    ImgDesc d = base_desc(im.h, im.w, im.c, im.sigma, p);
-    d.img = im.img;
-    d.out = im.out;
+    ImgDesc d = base_desc(imgs[i].h, imgs[i].w, imgs[i].c, imgs[i].sigma, p);
+    d.img = imgs[i].img;
+    d.out = imgs[i].out;
     b->hd.push_back(d);
-    size_t hw = (size_t)im.h * im.w;
-    b->off[WL_PIX][i] = (int)b->hw[WL_PIX].size();
-    for (int k = 0; k < (int)((hw + chunk - 1) / chunk); k++) b->hw[WL_PIX].push_back({i, k, 0, 0});
-    b->off[WL_PLANE][i] = (int)b->hw[WL_PLANE].size();
-    for (int k = 0; k < (int)((hw * im.c + chunk - 1) / chunk); k++) b->hw[WL_PLANE].push_back({i, k, 0, 0});
-    b->off[WL_MATCH][i] = (int)b->hw[WL_MATCH].size();
-    for (int y = 0; y < (d.nr + 3) / 4; y++)
-      for (int x = 0; x < (d.nc + 3) / 4; x++) b->hw[WL_MATCH].push_back({i, y, x, 0});
-    b->off[WL_FILTER][i] = (int)b->hw[WL_FILTER].size();
-    const int T = b->kp.tile;
-    for (int ch = 0; ch < im.c; ch++)
-      for (int y = 0; y < (d.nr + T - 1) / T; y++)
-        for (int x = 0; x < (d.nc + T - 1) / T; x++) b->hw[WL_FILTER].push_back({i, y, x, ch});
   }
-  for (int L = 0; L < kNumLists; L++) b->off[L][n] = (int)b->hw[L].size();
-  size_t desc_bytes = align_up(sizeof(ImgDesc) * n);
-  size_t work_bytes[kNumLists];
-  size_t all = tot + desc_bytes;
-  for (int L = 0; L < kNumLists; L++) {
-    work_bytes[L] = align_up(sizeof(Work) * std::max<size_t>(1, b->hw[L].size()));
-    all += work_bytes[L];
-  }
+  fill_prefix(b->hd.data(), n, b->kp, b->hprefix);
+  const size_t desc_bytes = align_up(sizeof(ImgDesc) * n);
+  const size_t pre_bytes = align_up(sizeof(int) * (n + 1));
+  const size_t all = tot + desc_bytes + LIST_KINDS * pre_bytes;
   if (hipMalloc((void**)&b->ws, all) != hipSuccess) {
     delete b;
     return BM3D_ERR_NOMEM;
   }
   b->ws_bytes = all;
   for (int i = 0; i < n; i++) bind_workspace(b->hd[i], b->ws + base[i], Ls[i]);
-  size_t o = tot;
-  b->dd = (ImgDesc*)(b->ws + o);
-  o += desc_bytes;
-  for (int L = 0; L < kNumLists; L++) {
-    b->dw[L] = (Work*)(b->ws + o);
-    o += work_bytes[L];
-  }
+  b->dd = (ImgDesc*)(b->ws + tot);
+  for (int L = 0; L < LIST_KINDS; L++) b->dprefix[L] = (int*)(b->ws + tot + desc_bytes + L * pre_bytes);
   bool ok = hipMemcpy(b->dd, b->hd.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
-  for (int L = 0; L < kNumLists && ok; L++)
-    if (!b->hw[L].empty())
-      ok = hipMemcpy(b->dw[L], b->hw[L].data(), sizeof(Work) * b->hw[L].size(), hipMemcpyHostToDevice) ==
-           hipSuccess;
+  for (int L = 0; L < LIST_KINDS && ok; L++)
+    ok = hipMemcpy(b->dprefix[L], b->hprefix[L].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) ==
+         hipSuccess;
   if (!ok) {
     (void)hipFree(b->ws);
     delete b;
@@ -515,6 +487,134 @@ extern "C" int bm3d_batch_destroy(bm3d_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->ws) (void)hipFree(b->ws);
   delete b;
+  return BM3D_OK;
+}
+
+// ============================================================ serving ticks
+// One tick advances every listed request by one stage.  Requests at the same
+// stage share one launch (their descriptors and prefix counts are packed
+// into a small table uploaded from pinned memory with one copy per tick).
+// Two table buffers alternate; a buffer is reused only after the event
+// recorded behind the tick that last used it has completed.
+struct bm3d_server {
+  int max_req = 0;
+  bm3d_params p;
+  KParams kp;
+  int cus = 256;
+  size_t table_bytes = 0;
+  char* host[2] = {nullptr, nullptr};
+  char* dev[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  bool used[2] = {false, false};
+  int cur = 0;
+};
+
+namespace {
+// per stage group: descriptors, prefix of its own list, prefix of the fill list
+size_t group_bytes(int m) { return align_up(sizeof(ImgDesc) * m) + 2 * align_up(sizeof(int) * (m + 1)); }
+}  // namespace
+
+extern "C" int bm3d_server_create(int max_requests, const bm3d_params* p, bm3d_server** out) {
+  if (!out || max_requests <= 0 || max_requests > 4096) return BM3D_ERR_ARG;
+  int e = check_params(p);
+  if (e) return e;
+  bm3d_server* s = new bm3d_server();
+  s->max_req = max_requests;
+  s->p = *p;
+  s->p.workspace = nullptr;
+  s->p.debug_nkept = nullptr;
+  s->kp = make_kparams(p);
+  s->cus = device_cus();
+  s->table_bytes = 7 * group_bytes(max_requests);
+  for (int k = 0; k < 2; k++) {
+    if (hipHostMalloc((void**)&s->host[k], s->table_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&s->dev[k], s->table_bytes) != hipSuccess ||
+        hipEventCreateWithFlags(&s->done[k], hipEventDisableTiming) != hipSuccess) {
+      bm3d_server_destroy(s);
+      return BM3D_ERR_NOMEM;
+    }
+  }
+  *out = s;
+  return BM3D_OK;
+}
+
+extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
+                                bm3d_stream_t stream) {
+  if (!s || (n > 0 && !reqs) || n < 0 || n > s->max_req) return BM3D_ERR_ARG;
+  int e;
+  for (int i = 0; i < n; i++) {
+    const bm3d_request& r = reqs[i];
+    if (r.stage < -1 || r.stage > 6) return BM3D_ERR_ARG;
+    if (r.stage < 0) continue;
+    if ((e = check_image(r.h, r.w, r.c))) return e;
+    if ((e = check_sigma(r.sigma))) return e;
+    if (!r.img || !r.out) return BM3D_ERR_ARG;
+    if (!r.workspace || r.workspace_bytes < layout(r.h, r.w, r.c, &s->p).total) return BM3D_ERR_WORKSPACE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int k = s->cur;
+  if (s->used[k] && hipEventSynchronize(s->done[k]) != hipSuccess) return BM3D_ERR_HIP;
+  // pack the stage groups
+  char* hb = s->host[k];
+  size_t off[7];
+  int cnt[7];
+  size_t o = 0;
+  for (int stg = 0; stg < 7; stg++) {
+    off[stg] = o;
+    cnt[stg] = 0;
+    ImgDesc* dsc = (ImgDesc*)(hb + o);
+    for (int i = 0; i < n; i++) {
+      const bm3d_request& r = reqs[i];
+      if (r.stage != stg) continue;
+      ImgDesc d = base_desc(r.h, r.w, r.c, r.sigma, &s->p);
+      d.img = r.img;
+      d.out = r.out;
+      bind_workspace(d, (char*)r.workspace, layout(r.h, r.w, r.c, &s->p));
+      dsc[cnt[stg]++] = d;
+    }
+    const int m = cnt[stg];
+    int* pre = (int*)(hb + o + align_up(sizeof(ImgDesc) * m));
+    int* pfill = (int*)((char*)pre + align_up(sizeof(int) * (m + 1)));
+    pre[0] = pfill[0] = 0;
+    for (int i = 0; i < m; i++) {
+      pre[i + 1] = pre[i] + items_of(list_of_stage(stg), dsc[i], s->kp.tile, elem_chunk());
+      pfill[i + 1] = pfill[i] + items_of(LIST_PLANE, dsc[i], s->kp.tile, elem_chunk());
+    }
+    o += group_bytes(m);
+  }
+  if (o > 0 && hipMemcpyAsync(s->dev[k], hb, o, hipMemcpyHostToDevice, st) != hipSuccess) return BM3D_ERR_HIP;
+  const int blocks = persistent_blocks(s->p, s->cus);
+  for (int stg = 0; stg < 7; stg++) {
+    const int m = cnt[stg];
+    if (!m) continue;
+    const char* db = s->dev[k] + off[stg];
+    const ImgDesc* dd = (const ImgDesc*)db;
+    const int* pre = (const int*)(db + align_up(sizeof(ImgDesc) * m));
+    const int* pfill = (const int*)((const char*)pre + align_up(sizeof(int) * (m + 1)));
+    const int* hpre = (const int*)(hb + off[stg] + align_up(sizeof(ImgDesc) * m));
+    const int* hfill = (const int*)((const char*)hpre + align_up(sizeof(int) * (m + 1)));
+    BatchRef br{dd, pre, m, 0, hpre[m]};
+    if (launch_batch(stg, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;
+    if (stg == STAGE_PREP || stg == STAGE_AGG1) {
+      BatchRef bf{dd, pfill, m, 0, hfill[m]};
+      if (launch_batch(STAGE_FILL, s->p.xform, bf, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;
+    }
+  }
+  if (hipEventRecord(s->done[k], st) != hipSuccess) return BM3D_ERR_HIP;
+  s->used[k] = true;
+  s->cur = 1 - k;
+  return BM3D_OK;
+}
+
+extern "C" int bm3d_server_destroy(bm3d_server* s) {
+  if (!s) return BM3D_ERR_ARG;
+  for (int k = 0; k < 2; k++) {
+    if (s->used[k]) (void)hipEventSynchronize(s->done[k]);
+    if (s->done[k]) (void)hipEventDestroy(s->done[k]);
+    if (s->host[k]) (void)hipHostFree(s->host[k]);
+    if (s->dev[k]) (void)hipFree(s->dev[k]);
+  }
+  delete s;
   return BM3D_OK;
 }
 

@@ -714,27 +714,40 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     }
   }
 
-  // ---- flush: num as accumulated; den = weight map (x) Kaiser window
+  // ---- flush: num as accumulated; den = weight map (x) Kaiser window,
+  // separably: each lane walks one region column down the rows, keeping the
+  // last 8 horizontal sums of the weight map in registers
   float* gnum = d.num + ch * hw;
   float* gden = d.den + ch * hw;
-  for (int i = l; i < RH * RW; i += 64) {
-    int y = i / RW, x = i - y * RW;
-    float nv = wnum[y * RP + x];
-    float dv = 0.f;
-    for (int u = 0; u < 8; u++) {
-      int py = y - u;
-      if (py < 0 || py >= g.ny) continue;
-      float rowsum = 0.f;
-      for (int v = 0; v < 8; v++) {
-        int px = x - v;
-        if (px >= 0 && px < g.nx) rowsum += kp.kaiser[v] * wW[py * WW + px];
+  float kw[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) kw[i] = kp.kaiser[i];
+  for (int x0 = 0; x0 < RW; x0 += 64) {
+    const int x = x0 + l;
+    float hsum[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) hsum[i] = 0.f;
+    for (int y = 0; y < RH; y++) {
+#pragma unroll
+      for (int i = 7; i > 0; i--) hsum[i] = hsum[i - 1];
+      float hsv = 0.f;
+      if (y < g.ny && x < RW) {
+        const float* wr = wW + y * WW;
+#pragma unroll
+        for (int v = 0; v < 8; v++) {
+          int px = x - v;
+          hsv += (px >= 0 && px < g.nx) ? kw[v] * wr[px] : 0.f;
+        }
       }
-      dv += kp.kaiser[u] * rowsum;
-    }
-    if (dv != 0.f) {
-      size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
-      atomicAdd(gnum + o, nv);
-      atomicAdd(gden + o, dv);
+      hsum[0] = hsv;
+      float dv = 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; u++) dv += kw[u] * hsum[u];
+      if (x < RW && dv != 0.f) {
+        size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
+        atomicAdd(gnum + o, wnum[y * RP + x]);
+        atomicAdd(gden + o, dv);
+      }
     }
   }
   wave_lds_sync();
@@ -759,8 +772,18 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wnum, wW);
 }
 
+// image holding global item i: largest k with prefix[k] <= i
+__device__ inline int find_img(const int* prefix, int n, int i) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 template <int STEP, class XF>
-__device__ void filter_block_batch(const ImgDesc* ds, const KParams& kp, const Work* wk, int nw, char* smem) {
+__device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
   frag* tabB = (frag*)smem;
@@ -772,9 +795,13 @@ __device__ void filter_block_batch(const ImgDesc* ds, const KParams& kp, const W
   const int wave = threadIdx.x >> 6;
   float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
   float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
-  for (int i = blockIdx.x * C::kWaves + wave; i < nw; i += gridDim.x * C::kWaves) {
-    const Work it = wk[i];
-    filter_wave_tile<STEP, XF>(ds[it.img], kp, it.y, it.x, it.ch, tabB, tabA, wnum, wW);
+  for (int i = br.begin + blockIdx.x * C::kWaves + wave; i < br.end; i += gridDim.x * C::kWaves) {
+    const int im = find_img(br.prefix, br.nimg, i);
+    const ImgDesc& d = br.ds[im];
+    const int j = i - br.prefix[im];
+    const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
+    const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
+    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wnum, wW);
   }
 }
 
@@ -798,43 +825,36 @@ __global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) k_filter(ImgDesc d
   filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
 }
 
-// batched: walk the work list
-__global__ void __launch_bounds__(kThreads) kb_elem(int stage, const ImgDesc* ds, const Work* wk, int nw) {
-  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
-    const Work it = wk[i];
-    const ImgDesc& d = ds[it.img];
-    if (stage == STAGE_PREP) {
-      prep_chunk(d, it.y);
-    } else if (stage == STAGE_AGG1) {
-      agg1_chunk(d, it.y);
-    } else {
-      agg2_chunk(d, it.y);
-    }
+// batched: each workgroup walks items begin + blockIdx.x, += gridDim.x
+__global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br) {
+  for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
+    const int im = find_img(br.prefix, br.nimg, i);
+    const ImgDesc& d = br.ds[im];
+    const int j = i - br.prefix[im];
+    if (stage == STAGE_PREP) prep_chunk(d, j);
+    else if (stage == STAGE_AGG1) agg1_chunk(d, j);
+    else if (stage == STAGE_AGG2) agg2_chunk(d, j);
+    else if (stage == STAGE_FILL) fill_chunk(d, j);
+    else lum_chunk(d, j);
   }
 }
-__global__ void __launch_bounds__(kThreads) kb_fill(const ImgDesc* ds, const Work* wk, int nw) {
-  for (int i = blockIdx.x; i < nw; i += gridDim.x) fill_chunk(ds[wk[i].img], wk[i].y);
-}
-__global__ void __launch_bounds__(kThreads) kb_match1(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
+template <int STEP>
+__global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
-  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
-    const Work it = wk[i];
-    match1_block(ds[it.img], kp, it.y, it.x, smem);
-    __syncthreads();
-  }
-}
-__global__ void __launch_bounds__(kThreads) kb_match2(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
-  extern __shared__ __align__(16) char smem[];
-  for (int i = blockIdx.x; i < nw; i += gridDim.x) {
-    const Work it = wk[i];
-    match2_block(ds[it.img], kp, it.y, it.x, smem);
+  for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
+    const int im = find_img(br.prefix, br.nimg, i);
+    const ImgDesc& d = br.ds[im];
+    const int j = i - br.prefix[im];
+    const int nbx = (d.nc + 3) / 4;
+    if (STEP == 1) match1_block(d, kp, j / nbx, j % nbx, smem);
+    else match2_block(d, kp, j / nbx, j % nbx, smem);
     __syncthreads();
   }
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) kb_filter(const ImgDesc* ds, KParams kp, const Work* wk, int nw) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) kb_filter(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
-  filter_block_batch<STEP, XF>(ds, kp, wk, nw, smem);
+  filter_block_batch<STEP, XF>(br, kp, smem);
 }
 
 // ============================================================ launchers ==
@@ -910,36 +930,35 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
   return post(s, sync);
 }
 
-int launch_batch(int stage, int xform, const ImgDesc* ds, const KParams& kp, const Work* wk, int nw,
-                 int blocks, hipStream_t s, bool sync) {
-  // blocks = 0: one workgroup per work item (per filter_waves() items for the
+int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, int blocks, hipStream_t s,
+                 bool sync) {
+  // blocks = 0: one workgroup per item (per filter_waves() items for the
   // filters); otherwise a persistent grid of that many workgroups.
+  const int nw = br.end - br.begin;
   if (nw <= 0) return 0;
   int grid = (blocks <= 0 || blocks > nw) ? nw : blocks;
   switch (stage) {
     case STAGE_PREP:
     case STAGE_AGG1:
     case STAGE_AGG2:
-      hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, ds, wk, nw);
-      break;
     case STAGE_FILL:
-      hipLaunchKernelGGL(kb_fill, dim3(grid), dim3(kThreads), 0, s, ds, wk, nw);
+    case STAGE_LUM:
+      hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, br);
       break;
     case STAGE_MATCH1: {
       size_t b = match1_lds_bytes(kp.S1);
-      lds_attr(kb_match1, b);
-      hipLaunchKernelGGL(kb_match1, dim3(grid), dim3(kThreads), b, s, ds, kp, wk, nw);
+      lds_attr(kb_match<1>, b);
+      hipLaunchKernelGGL(kb_match<1>, dim3(grid), dim3(kThreads), b, s, br, kp);
       break;
     }
     case STAGE_MATCH2: {
       size_t b = match2_lds_bytes(kp.S2, kThreads / 64);
-      lds_attr(kb_match2, b);
-      hipLaunchKernelGGL(kb_match2, dim3(grid), dim3(kThreads), b, s, ds, kp, wk, nw);
+      lds_attr(kb_match<2>, b);
+      hipLaunchKernelGGL(kb_match<2>, dim3(grid), dim3(kThreads), b, s, br, kp);
       break;
     }
     case STAGE_FILTER1:
     case STAGE_FILTER2: {
-      // work items are wave tiles; a workgroup runs filter_waves() of them at once
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
       const int wv = filter_waves(xform);
       int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
@@ -947,7 +966,7 @@ int launch_batch(int stage, int xform, const ImgDesc* ds, const KParams& kp, con
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
     lds_attr(kb_filter<STEP, XF>, b);                                                     \
-    hipLaunchKernelGGL((kb_filter<STEP, XF>), dim3(g), dim3(64 * wv), b, s, ds, kp, wk, nw); \
+    hipLaunchKernelGGL((kb_filter<STEP, XF>), dim3(g), dim3(64 * wv), b, s, br, kp);      \
   } while (0)
       if (stage == STAGE_FILTER1) {
         if (xform == 0) LAUNCH_FB(1, XF32); else if (xform == 1) LAUNCH_FB(1, XBF16); else LAUNCH_FB(1, XF16);

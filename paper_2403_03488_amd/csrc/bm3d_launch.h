@@ -19,15 +19,41 @@ enum Stage {
   STAGE_LUM = 8    // step-2 luminance from a planar basic estimate
 };
 
-// One item of a batched stage: image, tile row/column (or elementwise chunk
-// in y), channel.
-struct Work {
-  int img, y, x, ch;
+// Batched launches decode their work arithmetically: for every image the
+// number of items of a stage is a function of its size (elementwise chunks,
+// 4x4-reference matching blocks, or channel x filter tiles), so a launch only
+// needs the image descriptors and the per-image prefix counts.
+enum ListKind { LIST_PIX = 0, LIST_PLANE = 1, LIST_MATCH = 2, LIST_FILTER = 3, LIST_KINDS = 4 };
+
+__host__ __device__ inline int list_of_stage(int stage) {
+  switch (stage) {
+    case STAGE_PREP: case STAGE_AGG1: case STAGE_AGG2: case STAGE_LUM: return LIST_PIX;
+    case STAGE_FILL: return LIST_PLANE;
+    case STAGE_MATCH1: case STAGE_MATCH2: return LIST_MATCH;
+    default: return LIST_FILTER;
+  }
+}
+
+__host__ __device__ inline int items_of(int list, const ImgDesc& d, int tile, int chunk) {
+  const long long hw = (long long)d.h * d.w;
+  switch (list) {
+    case LIST_PIX: return (int)((hw + chunk - 1) / chunk);
+    case LIST_PLANE: return (int)((hw * d.c + chunk - 1) / chunk);
+    case LIST_MATCH: return ((d.nr + 3) / 4) * ((d.nc + 3) / 4);
+    default: return d.c * ((d.nr + tile - 1) / tile) * ((d.nc + tile - 1) / tile);
+  }
+}
+
+struct BatchRef {
+  const ImgDesc* ds;   // device descriptors of the images
+  const int* prefix;   // device prefix item counts for the stage's list kind (nimg+1)
+  int nimg;
+  int begin, end;      // item range of this launch
 };
 
 int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s, bool sync);
-int launch_batch(int stage, int xform, const ImgDesc* dev_descs, const KParams& kp, const Work* dev_work,
-                 int nwork, int blocks, hipStream_t s, bool sync);
+int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, int blocks, hipStream_t s,
+                 bool sync);
 size_t stage_lds_bytes(int stage, int xform, const KParams& kp);
 int elem_chunk();
 int filter_block_waves(int xform);

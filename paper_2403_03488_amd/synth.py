@@ -55,22 +55,22 @@ def smooth_texture_image(rng: np.random.Generator, h: int, w: int,
                          n_regions: int = 12, n_textures: int = 6) -> np.ndarray:
     """Voronoi regions with linear gradients, plus rotated sinusoid/checkerboard
     texture patches with periods 3-16 px."""
-    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
     seeds = np.stack([rng.uniform(0, h, n_regions), rng.uniform(0, w, n_regions)], 1)
     # nearest seed per pixel, computed in row blocks to bound memory
     label = np.empty((h, w), np.int32)
-    for r0 in range(0, h, 256):
-        dy = yy[r0:r0 + 256, :, None] - seeds[None, None, :, 0]
-        dx = xx[r0:r0 + 256, :, None] - seeds[None, None, :, 1]
-        label[r0:r0 + 256] = np.argmin(dy * dy + dx * dx, axis=2)
+    xs = np.arange(w, dtype=np.float64)
+    dx2 = (xs[:, None] - seeds[None, :, 1]) ** 2                      # [w, k]
+    for r0 in range(0, h, 64):
+        ys = np.arange(r0, min(h, r0 + 64), dtype=np.float64)
+        dy2 = (ys[:, None] - seeds[None, :, 0]) ** 2                  # [rows, k]
+        label[r0:r0 + 64] = np.argmin(dy2[:, None, :] + dx2[None, :, :], axis=2)
     img = np.empty((h, w))
     for k in range(n_regions):
         a = rng.uniform(30, 225)
         b, c = rng.uniform(-0.5, 0.5), rng.uniform(-0.5, 0.5)
         # gradients are referenced to the region's seed so levels stay in range
-        val = a + b * (xx - seeds[k, 1]) + c * (yy - seeds[k, 0])
-        m = label == k
-        img[m] = val[m]
+        yy, xx = np.nonzero(label == k)
+        img[yy, xx] = a + b * (xx.astype(np.float64) - seeds[k, 1]) + c * (yy.astype(np.float64) - seeds[k, 0])
     for _ in range(n_textures):
         th = int(rng.integers(min(h, 48), min(h, 160) + 1))
         tw = int(rng.integers(min(w, 48), min(w, 160) + 1))
@@ -207,3 +207,43 @@ def psnr(ref: np.ndarray, est: np.ndarray) -> float:
     d = ref.astype(np.float64) - est.astype(np.float64)
     mse = float(np.mean(d * d))
     return float("inf") if mse == 0 else 10.0 * math.log10(255.0 ** 2 / mse)
+
+
+# ---------------------------------------------------------- serving trace ---
+
+
+def serving_canvases(side: int = 4096, seed: int = 4000):
+    """Large seeded canvases that serving requests are cropped from: grey and
+    colour piecewise-smooth/texture content, grey and colour moire."""
+    r = np.random.default_rng(seed)
+    g = smooth_texture_image(r, side, side, n_regions=48, n_textures=96)
+    col = mixed_colour_image(r, side, side)
+    m = moire_image(r, side, side)
+    mc = np.stack([moire_image(r, side, side) for _ in range(3)], axis=2)
+    return {"grey": g, "colour": col, "grey_moire": m, "colour_moire": mc}
+
+
+def serving_specs(n: int, rate: float, max_side: int = 4096, seed: int = 4001):
+    """Poisson arrivals at `rate` requests/s; sides log-uniform in
+    [256, max_side]; 70 % grey / 30 % colour; sigma ~ U[5, 60]; 30 % moire."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    lo, hi = math.log(256), math.log(max_side)
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        hh = int(round(math.exp(rng.uniform(lo, hi))))
+        ww = int(round(math.exp(rng.uniform(lo, hi))))
+        colour = rng.random() < 0.3
+        moire = rng.random() < 0.3
+        kind = ("colour" if colour else "grey") + ("_moire" if moire else "")
+        out.append({"rid": i, "arrival": t, "h": hh, "w": ww, "c": 3 if colour else 1,
+                    "sigma": float(rng.uniform(5.0, 60.0)), "kind": kind,
+                    "y0": int(rng.integers(0, max_side - hh + 1)),
+                    "x0": int(rng.integers(0, max_side - ww + 1)), "noise_seed": 10_000 + i})
+    return out
+
+
+def crop_clean(canvases, spec):
+    a = canvases[spec["kind"]]
+    return np.ascontiguousarray(a[spec["y0"]:spec["y0"] + spec["h"], spec["x0"]:spec["x0"] + spec["w"]])

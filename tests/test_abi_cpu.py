@@ -1,0 +1,136 @@
+"""The C ABI on the CPU: the library loads without a GPU, exports every entry
+point declared in include/bm3d.h, and rejects invalid arguments on the host
+before anything is enqueued (no GPU call is reached)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bm3d.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    lib = os.path.join(ROOT, "paper_2403_03488_amd", "libbm3d_mi355x.so")
+    if not os.path.exists(lib):
+        from paper_2403_03488_amd import build
+        build.build()
+    from paper_2403_03488_amd import bm3d
+    return bm3d
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bm3d_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("bm3d_block_match", "bm3d_collab_filter", "bm3d_aggregate", "bm3d_denoise"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(B):
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(B.library_symbols())
+
+
+def test_struct_layout_matches_header(B):
+    # bm3d_params: 4 ints, 4 floats, 4 ints/unsigned, 2 pointers, size_t
+    assert ctypes.sizeof(B.Params) == 4 * 4 + 4 * 4 + 4 * 4 + 8 + 8 + 8
+    assert ctypes.sizeof(B.ImageDesc) == 8 + 8 + 3 * 4 + 4
+
+
+def test_defaults_and_geometry(B):
+    p = B.params_default(25.0)
+    assert (p.search_ht, p.search_wie, p.n_ht, p.n_wie) == (32, 32, 16, 32)
+    assert abs(p.lambda_ht - 2.7) < 1e-6 and p.kaiser_beta == 2.0
+    assert (p.tau_ht, p.tau_wie) == (2500.0, 400.0)
+    q = B.params_default(50.0)
+    assert (q.tau_ht, q.tau_wie) == (5000.0, 3500.0)
+    assert B.num_refs(512, 512) == 169 * 169
+    assert B.num_refs(321, 481) == 106 * 159
+    assert B.num_refs(8, 8) == 1 and B.num_refs(7, 100) == 0
+    assert B.workspace_size(512, 512, 1, p) > 512 * 512 * 17
+    assert B.workspace_size(4, 512, 1, p) == 0
+    assert B.strerror(0) == "ok" and "argument" in B.strerror(-1)
+
+
+def test_host_validation_rejects_before_enqueue(B):
+    L = B._lib
+    p = B.params_default(25.0)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ref = ctypes.byref
+    # bad image sizes / channels / sigma
+    assert L.bm3d_denoise(fake, 7, 64, 1, 25.0, ref(p), fake, None) == -1
+    assert L.bm3d_denoise(fake, 64, 64, 2, 25.0, ref(p), fake, None) == -1
+    assert L.bm3d_denoise(fake, 64, 64, 1, float("nan"), ref(p), fake, None) == -1
+    assert L.bm3d_denoise(fake, 64, 64, 1, -1.0, ref(p), fake, None) == -1
+    assert L.bm3d_denoise(None, 64, 64, 1, 25.0, ref(p), fake, None) == -1
+    # missing workspace
+    assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(p), fake, None) == -3
+    small = p.copy()
+    small.workspace = 0x2000
+    small.workspace_bytes = 10
+    assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(small), fake, None) == -3
+    # invalid parameters
+    for field, val in (("n_wie", 24), ("n_ht", 0), ("search_ht", 33), ("search_wie", 0),
+                       ("lambda_ht", -1.0), ("tau_wie", float("nan")), ("xform", 7),
+                       ("kaiser_beta", float("inf")), ("tile_refs", 17)):
+        q = p.copy()
+        setattr(q, field, val)
+        assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(q), fake, None) == -1, field
+    big = p.copy()
+    big.tile_refs = 16  # legal range, but its LDS footprint does not fit
+    assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(big), fake, None) == -2
+    # stage entry points
+    assert L.bm3d_block_match(fake, 1, 64, 64, 1, ref(p), fake, fake, None) == -1  # step 1 needs uint8
+    assert L.bm3d_block_match(fake, 0, 64, 64, 3, ref(p), fake, fake, None) == -1
+    assert L.bm3d_collab_filter(fake, fake, 64, 64, 1, 25.0, 1, fake, fake, ref(p), fake, fake,
+                                None) == -1  # step 1 takes no basic estimate
+    assert L.bm3d_collab_filter(fake, None, 64, 64, 1, 25.0, 2, fake, fake, ref(p), fake, fake,
+                                None) == -1  # step 2 needs one
+    assert L.bm3d_aggregate(fake, None, 64, 64, 1, 1, fake, None) == -1
+    assert L.bm3d_prepare(fake, 64, 64, 4, fake, fake, None) == -1
+    assert L.bm3d_luminance(None, 64, 64, 1, fake, None) == -1
+    # batch plans
+    h = ctypes.c_void_p()
+    arr = (B.ImageDesc * 1)(B.ImageDesc(0x1000, 0x2000, 64, 64, 2, 25.0))
+    assert L.bm3d_batch_create(arr, 1, ref(p), ref(h)) == -1
+    assert L.bm3d_batch_create(arr, 0, ref(p), ref(h)) == -1
+    assert L.bm3d_batch_run(None, None) == -1
+    assert L.bm3d_batch_launch(None, None) == -1
+    assert L.bm3d_batch_run_stages(None, 0, 1, 0, 6, None) == -1
+
+
+def test_binding_refuses_host_tensors(B):
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        B._ptr(torch.zeros(4), None, "x")
+
+
+def test_server_validation_on_host(B):
+    L = B._lib
+    p = B.params_default(25.0)
+    h = ctypes.c_void_p()
+    assert L.bm3d_server_create(0, ctypes.byref(p), ctypes.byref(h)) == -1
+    bad = p.copy()
+    bad.n_ht = 3
+    assert L.bm3d_server_create(4, ctypes.byref(bad), ctypes.byref(h)) == -1
+    assert L.bm3d_server_tick(None, None, 0, None) == -1
+    assert L.bm3d_server_destroy(None) == -1
+
+
+def test_footprint_model(B):
+    from paper_2403_03488_amd import serve
+    p = B.params_default(25.0)
+    f = serve.footprint(4096, 4096, 3, p)
+    # planar, basic, num, den (4 x 12 B/px), luminances (5 B/px), in+out (15 B/px),
+    # groups (16 + 32 indices per reference, ~1 reference per 9 px: ~21 B/px)
+    assert 80 * 4096 * 4096 < f < 100 * 4096 * 4096
