@@ -58,6 +58,51 @@ def work_models(h, w, S, cnt1, cnt2, c=1):
     }
 
 
+def measured_traffic(kernel, images):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/hbm_traffic_*.json), if they were taken on the current kernel
+    sources; None otherwise."""
+    import glob
+    import hashlib
+    src = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(
+        ROOT, "paper_2403_03488_amd", "csrc", "*"))))
+    sha = hashlib.sha256(src.encode()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
+        rec = json.load(open(path))
+        if rec.get("source_sha") == sha and kernel in rec.get("kernels", {}):
+            k = rec["kernels"][kernel]
+            return images * (k["fetch_bytes_per_image"] + k["write_bytes_per_image"])
+    return None
+
+
+def single_image_checks(torch, bm3d, synth, p, imgs, outs, samples, sigma, H, W, B):
+    """Single-image latency (plain path) and the FP32 comparison on image 0."""
+    ws = torch.empty(bm3d.workspace_size(H, W, 1, p), dtype=torch.uint8, device="cuda")
+    lat = []
+    for i in range(30):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bm3d.denoise(imgs[i % B], sigma, p, out=outs[0], workspace=ws)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    lat_ms = sorted(1e3 * x for x in lat[5:])
+    p32 = bm3d.params_default(sigma, xform=0, tile_refs=p.tile_refs)
+    ws32 = torch.empty(bm3d.workspace_size(H, W, 1, p32), dtype=torch.uint8, device="cuda")
+    o32 = bm3d.denoise(imgs[0], sigma, p32, workspace=ws32)
+    olo = bm3d.denoise(imgs[0], sigma, p, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(10):
+        bm3d.denoise(imgs[i % B], sigma, p32, out=outs[1], workspace=ws32)
+    torch.cuda.synchronize()
+    fp32_single = 10 * H * W / 1e6 / (time.perf_counter() - t)
+    clean0 = samples[0].clean
+    psnr32 = synth.psnr(clean0, o32.cpu().numpy())
+    psnrlo = synth.psnr(clean0, olo.cpu().numpy())
+
+    return lat_ms, fp32_single, psnr32, psnrlo
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +113,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="only the timed batched pass and stage timings (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
+    if args.quick:
+        args.no_autotune = args.no_cpu_baseline = True
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the design notes for how the work would shard)", file=sys.stderr)
@@ -161,35 +212,23 @@ def main():
     bound, _, peak, unit = kinds[dom]
     achieved = work[dom] / (stage_ms[dom] * 1e-3)
     roof = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
-            "unit": unit, "frac": achieved / peak, "traffic": None,
+            "unit": unit, "frac": achieved / peak,
+            "traffic": measured_traffic(dom, B) if args.xform == "bf16" else None,
             "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom]}
     per_stage = {k: {"ms": stage_ms[k], "frac": (work[k] / (stage_ms[k] * 1e-3)) / kinds[k][2]}
                  for k in work}
 
-    # single-image latency (plain path) and the FP32 comparison on image 0
-    ws = torch.empty(bm3d.workspace_size(H, W, 1, p), dtype=torch.uint8, device="cuda")
-    lat = []
-    for i in range(30):
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        bm3d.denoise(imgs[i % B], sigma, p, out=outs[0], workspace=ws)
+        dst.copy_(src)
         torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t)
-    lat_ms = sorted(1e3 * x for x in lat[5:])
-    p32 = bm3d.params_default(sigma, xform=0, tile_refs=p.tile_refs)
-    ws32 = torch.empty(bm3d.workspace_size(H, W, 1, p32), dtype=torch.uint8, device="cuda")
-    o32 = bm3d.denoise(imgs[0], sigma, p32, workspace=ws32)
-    olo = bm3d.denoise(imgs[0], sigma, p, workspace=ws)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(10):
-        bm3d.denoise(imgs[i % B], sigma, p32, out=outs[1], workspace=ws32)
-    torch.cuda.synchronize()
-    fp32_single = 10 * H * W / 1e6 / (time.perf_counter() - t)
-    clean0 = samples[0].clean
-    psnr32 = synth.psnr(clean0, o32.cpu().numpy())
-    psnrlo = synth.psnr(clean0, olo.cpu().numpy())
-
+        del src, dst
+    lat_ms, fp32_single, psnr32, psnrlo = [float("nan")], float("nan"), float("nan"), float("nan")
+    if not args.quick:
+        lat_ms, fp32_single, psnr32, psnrlo = single_image_checks(torch, bm3d, synth, p, imgs, outs,
+                                                                  samples, sigma, H, W, B)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
