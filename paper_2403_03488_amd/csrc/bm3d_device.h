@@ -68,6 +68,16 @@ struct KParams {
   float kaiser[8];  // 1-D Kaiser window
 };
 
+// ------------------------------------------------- global-memory access ---
+// Pointers reached through a descriptor in memory are generic to the
+// compiler; these force global (not flat) instructions.
+#define BM3D_GLOBAL __attribute__((address_space(1)))
+template <class T> __device__ inline T ldg(const T* p) { return *(const BM3D_GLOBAL T*)p; }
+template <class T> __device__ inline void stg(T* p, T v) { *(BM3D_GLOBAL T*)p = v; }
+__device__ inline void gadd(float* p, float v) {
+  __hip_atomic_fetch_add((BM3D_GLOBAL float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ----------------------------------------------------- wave primitives ---
 __device__ inline int lane_id() { return __lane_id(); }
 

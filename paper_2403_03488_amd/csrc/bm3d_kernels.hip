@@ -184,11 +184,23 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
   uint32_t* keys = (uint32_t*)(nq + (size_t)(S + 9) * 48);
   int32_t* rs = (int32_t*)keys;
 
-  // int8 region (luminance - 128); columns beyond the image read as 0
-  for (int i = tid; i < RR * 64; i += blockDim.x) {
-    int y = i >> 6, x = i & 63;
-    int gx = g.ux0 + x;
-    reg[i] = gx < w ? (uint8_t)(d.lum8[(size_t)(g.uy0 + y) * w + gx] ^ 0x80u) : (uint8_t)0;
+  // int8 region (luminance - 128); columns beyond the image read as 0.
+  // All loads of a thread are issued before any is used.
+  {
+    constexpr int kMaxIt = (kMaxS + 16) * 64 / 256;
+    uint8_t v[kMaxIt];
+#pragma unroll
+    for (int k = 0; k < kMaxIt; k++) {
+      int i = tid + k * 256;
+      int y = min(i >> 6, RR - 1), x = i & 63;
+      int gx = min(g.ux0 + x, w - 1);
+      v[k] = ldg(d.lum8 + (size_t)(g.uy0 + y) * w + gx);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxIt; k++) {
+      int i = tid + k * 256;
+      if (i < RR * 64) reg[i] = (g.ux0 + (i & 63) < w) ? (uint8_t)(v[k] ^ 0x80u) : (uint8_t)0;
+    }
   }
   __syncthreads();
   // |q|^2 of every union candidate: 8-wide row sums, then 8-tall column sums
@@ -284,8 +296,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx1 + r * nmax;
     if (l == 0) {
-      o[0] = ry * w + rx;
-      d.cnt1[r] = n;
+      stg(o, ry * w + rx);
+      stg(d.cnt1 + r, n);
     }
     if (l + 1 < nmax) {
       int gi = -1;
@@ -293,7 +305,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
         int widx = (int)(sel & 1023u);
         gi = (wy + widx / SW) * w + wx + widx % SW;
       }
-      o[l + 1] = gi;
+      stg(o + l + 1, gi);
     }
   }
 }
@@ -316,10 +328,21 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
   float* reg = (float*)smem;
   uint64_t* bufs = (uint64_t*)(smem + (((size_t)(S + 16) * kM2Pitch * 4 + 15) & ~(size_t)15));
 
-  for (int i = tid; i < RR * kM2Pitch; i += blockDim.x) {
-    int y = i / kM2Pitch, x = i - y * kM2Pitch;
-    int gx = g.ux0 + x;
-    reg[i] = gx < w ? d.lumf[(size_t)(g.uy0 + y) * w + gx] : 0.f;
+  {
+    constexpr int kMaxIt = ((kMaxS + 16) * kM2Pitch + 255) / 256;
+    float v[kMaxIt];
+#pragma unroll
+    for (int k = 0; k < kMaxIt; k++) {
+      int i = tid + k * 256;
+      int y = min(i / kM2Pitch, RR - 1), x = i % kM2Pitch;
+      int gx = min(g.ux0 + x, w - 1);
+      v[k] = ldg(d.lumf + (size_t)(g.uy0 + y) * w + gx);
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxIt; k++) {
+      int i = tid + k * 256;
+      if (i < RR * kM2Pitch) reg[i] = (g.ux0 + i % kM2Pitch < w) ? v[k] : 0.f;
+    }
   }
   __syncthreads();
 
@@ -370,8 +393,8 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx2 + r * nmax;
     if (l == 0) {
-      o[0] = ry * w + rx;
-      d.cnt2[r] = n;
+      stg(o, ry * w + rx);
+      stg(d.cnt2 + r, n);
     }
     if (l + 1 < nmax) {
       int gi = -1;
@@ -379,7 +402,7 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
         int widx = (int)(sel & 1023u);
         gi = (wy + widx / SW) * w + wx + widx % SW;
       }
-      o[l + 1] = gi;
+      stg(o + l + 1, gi);
     }
   }
 }
@@ -518,7 +541,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   for (int j = 0; j < nrefs; j++) {
     const int ri = g.ri0 + j / g.nci, ci = g.ci0 + j % g.nci;
     const size_t r = (size_t)ri * d.nc + ci;
-    const int n = min(max(cnt[r], 1), nmax);
+    const int n = min(max(ldg(cnt + r), 1), nmax);
     const int NG = n > 16 ? 2 : 1;
     const float rsn = n == 1 ? 1.f : n == 2 ? 0.70710678118654752f : n == 4 ? 0.5f
                     : n == 8 ? 0.35355339059327376f : n == 16 ? 0.25f : 0.17677669529663688f;
@@ -528,7 +551,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     for (int gt = 0; gt < 2; gt++) {
       int gm = 16 * gt + col;
       mv[gt] = gt < NG && gm < n;
-      int gi = idx[r * nmax + (mv[gt] ? gm : 0)];
+      int gi = ldg(idx + r * nmax + (mv[gt] ? gm : 0));
       int yy = gi >= 0 ? gi / w : -1, xx = gi >= 0 ? gi - yy * w : -1;
       // a member must lie in the tile's search region (true for any grouping
       // made with the same window rule); anything else is ignored
@@ -552,7 +575,9 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           const float* src = noisy + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
           f32x4 a;
 #pragma unroll
-          for (int v = 0; v < 4; v++) a[v] = mv[gt] ? src[v] - centre : 0.f;
+          for (int v = 0; v < 4; v++) a[v] = ldg(src + v);  // always a valid pixel
+#pragma unroll
+          for (int v = 0; v < 4; v++) a[v] = mv[gt] ? a[v] - centre : 0.f;
           frag af = XF::cvt(a);
 #pragma unroll
           for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
@@ -583,7 +608,9 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
             const float* src = basic + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
             f32x4 a;
 #pragma unroll
-            for (int v = 0; v < 4; v++) a[v] = mv[gt] ? src[v] - centre : 0.f;
+            for (int v = 0; v < 4; v++) a[v] = ldg(src + v);  // always a valid pixel
+#pragma unroll
+            for (int v = 0; v < 4; v++) a[v] = mv[gt] ? a[v] - centre : 0.f;
             frag af = XF::cvt(a);
 #pragma unroll
             for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
@@ -745,8 +772,8 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       for (int u = 0; u < 8; u++) dv += kw[u] * hsum[u];
       if (x < RW && dv != 0.f) {
         size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
-        atomicAdd(gnum + o, wnum[y * RP + x]);
-        atomicAdd(gden + o, dv);
+        gadd(gnum + o, wnum[y * RP + x]);
+        gadd(gden + o, dv);
       }
     }
   }
