@@ -145,6 +145,24 @@ __device__ inline float wave_sum_f(float v) {
   return v;
 }
 
+// Sum over the wave, returned as a wave-uniform value.  Rows of 16 lanes
+// are reduced with DPP moves (quad swaps, then half-row and row mirrors), the
+// four row sums are combined through lane reads.
+template <int CTRL> __device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float wave_sum_uniform(float v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  v += dpp_f<0x140>(v);  // row_mirror
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) +
+          __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+}
+
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -220,28 +238,14 @@ struct XF32 {
 };
 struct XBF16 {
   typedef bf16x4 frag;
-  static __device__ inline frag cvt(f32x4 a) {
-    frag r;
-    r[0] = (__bf16)a[0];
-    r[1] = (__bf16)a[1];
-    r[2] = (__bf16)a[2];
-    r[3] = (__bf16)a[3];
-    return r;
-  }
+  static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
 };
 struct XF16 {
   typedef f16x4 frag;
-  static __device__ inline frag cvt(f32x4 a) {
-    frag r;
-    r[0] = (_Float16)a[0];
-    r[1] = (_Float16)a[1];
-    r[2] = (_Float16)a[2];
-    r[3] = (_Float16)a[3];
-    return r;
-  }
+  static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
   }

@@ -435,14 +435,18 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
   static constexpr int kWaves = sizeof(frag) == 16 ? 4 : 6;  // waves per workgroup
+  // staging row pitch: member rows 68 floats apart, so the 16 lanes of a
+  // fragment row write to different LDS banks
+  static constexpr int kSP = 68;
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag) + 64 * 4; }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
   // row pitch of the numerator region: = 8 (mod 16) so the 8 rows of a
   // member patch fall in different LDS banks
   static __host__ __device__ int pitch(int rw) { return rw + ((24 - rw % 16) % 16); }
   static __host__ __device__ int rw(int S, int T) { return 3 * (T - 1) + S; }
+  // numerator region, weight map, staging [16][kSP], one spare slot per lane
   static __host__ __device__ size_t per_wave(int S, int T) {
-    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + (size_t)rw(S, T) * rw(S, T) + 16 * 64) * 4;
+    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + (size_t)rw(S, T) * rw(S, T) + 16 * kSP + 64) * 4;
   }
   static __host__ __device__ size_t bytes(int S, int T) { return tables() + kWaves * per_wave(S, T); }
 };
@@ -506,6 +510,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
                                  const typename XF::frag* __restrict__ tabB,
                                  const typename XF::frag* __restrict__ tabA, float* wnum, float* wW) {
   typedef typename XF::frag frag;
+  typedef FilterCfg<XF> C;
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int nmax = STEP == 1 ? kp.n1 : kp.n2;
   const int32_t* __restrict__ idx = STEP == 1 ? d.idx1 : d.idx2;
@@ -517,9 +522,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const int q = l >> 4, col = l & 15;
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, T, ty, tx);
   const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
-  const int RP = FilterCfg<XF>::pitch(RW);  // its row pitch
-  const int WW = g.nx;                      // weight map row pitch (positions)
-  float* wst = wW + FilterCfg<XF>::rw(S, T) * FilterCfg<XF>::rw(S, T);  // staging [16][64]
+  const int RP = C::pitch(RW);             // its row pitch
+  const int WW = g.nx;                     // weight map row pitch (positions)
+  float* wst = wW + C::rw(S, T) * C::rw(S, T);  // staging [16][kSP]
+  const int spare = (int)(wst + 16 * C::kSP - wnum) + l;  // this lane's spare slot
 
   for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
   for (int i = l; i < g.ny * WW; i += 64) wW[i] = 0.f;
@@ -536,12 +542,14 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     Ku[i] = kp.kaiser[2 * i + (q >> 1)];
     Kv[i] = kp.kaiser[4 * (q & 1) + i];
   }
+  const int ru = l >> 3, rv = l & 7;
 
   const int nrefs = g.nri * g.nci;
   for (int j = 0; j < nrefs; j++) {
     const int ri = g.ri0 + j / g.nci, ci = g.ci0 + j % g.nci;
     const size_t r = (size_t)ri * d.nc + ci;
-    const int n = min(max(ldg(cnt + r), 1), nmax);
+    // group size and everything derived from it are wave-uniform
+    const int n = __builtin_amdgcn_readfirstlane(min(max(ldg(cnt + r), 1), nmax));
     const int NG = n > 16 ? 2 : 1;
     const float rsn = n == 1 ? 1.f : n == 2 ? 0.70710678118654752f : n == 4 ? 0.5f
                     : n == 8 ? 0.35355339059327376f : n == 16 ? 0.25f : 0.17677669529663688f;
@@ -560,25 +568,38 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       my[gt] = inside ? yy : g.uy0;
       mx[gt] = inside ? xx : g.ux0;
     }
+    // Hadamard fragments: Hf[a][b] holds block (a, b) of the n-point matrix
+    // (symmetric, so it serves as both A and B operand)
+    frag Hf[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) Hf[a][b] = had_frag<XF>(a, b, n);
 
-    // ---- forward: 2-D DCT then WHT (noisy; and basic in step 2)
+    // ---- forward: 2-D DCT then WHT of the noisy (and in step 2 the basic) group
     f32x4 D2[2][4], D2b[2][4];
-    {
+#pragma unroll
+    for (int src_i = 0; src_i < (STEP == 2 ? 2 : 1); src_i++) {
+      const float* __restrict__ src0 = src_i == 0 ? noisy : basic;
       f32x4 D1[2][4];
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
+        f32x4 a[4];
+#pragma unroll
+        for (int kt = 0; kt < 4; kt++) {
+          const float* src = src0 + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+#pragma unroll
+          for (int v = 0; v < 4; v++) a[kt][v] = ldg(src + v);  // always a valid pixel
+        }
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
 #pragma unroll
         for (int kt = 0; kt < 4; kt++) {
-          const float* src = noisy + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
-          f32x4 a;
+          f32x4 c;
 #pragma unroll
-          for (int v = 0; v < 4; v++) a[v] = ldg(src + v);  // always a valid pixel
-#pragma unroll
-          for (int v = 0; v < 4; v++) a[v] = mv[gt] ? a[v] - centre : 0.f;
-          frag af = XF::cvt(a);
+          for (int v = 0; v < 4; v++) c[v] = mv[gt] ? a[kt][v] - centre : 0.f;
+          frag af = XF::cvt(c);
 #pragma unroll
           for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
         }
@@ -592,43 +613,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
           for (int gt = 0; gt < 2; gt++) {
             if (gt >= NG) break;
-            acc = XF::mma(had_frag<XF>(tt, gt, n), XF::cvt(D1[gt][nt]), acc);
+            acc = XF::mma(Hf[tt][gt], XF::cvt(D1[gt][nt]), acc);
           }
-          D2[tt][nt] = acc * rsn;
-        }
-      }
-      if (STEP == 2) {
-#pragma unroll
-        for (int gt = 0; gt < 2; gt++) {
-          if (gt >= NG) break;
-#pragma unroll
-          for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
-#pragma unroll
-          for (int kt = 0; kt < 4; kt++) {
-            const float* src = basic + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
-            f32x4 a;
-#pragma unroll
-            for (int v = 0; v < 4; v++) a[v] = ldg(src + v);  // always a valid pixel
-#pragma unroll
-            for (int v = 0; v < 4; v++) a[v] = mv[gt] ? a[v] - centre : 0.f;
-            frag af = XF::cvt(a);
-#pragma unroll
-            for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
-          }
-        }
-#pragma unroll
-        for (int tt = 0; tt < 2; tt++) {
-          if (tt >= NG) break;
-#pragma unroll
-          for (int nt = 0; nt < 4; nt++) {
-            f32x4 acc = zero4();
-#pragma unroll
-            for (int gt = 0; gt < 2; gt++) {
-              if (gt >= NG) break;
-              acc = XF::mma(had_frag<XF>(tt, gt, n), XF::cvt(D1[gt][nt]), acc);
-            }
-            D2b[tt][nt] = acc * rsn;
-          }
+          if (src_i == 0) D2[tt][nt] = acc * rsn;
+          else D2b[tt][nt] = acc * rsn;
         }
       }
     }
@@ -658,7 +646,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
               float sb = D2b[tt][nt][v] + (isdc ? off : 0.f);
               float b2 = sb * sb;
               float dd = b2 + sig2;
-              float W = dd > 0.f ? b2 / dd : 1.f;
+              float W = dd > 0.f ? b2 * __builtin_amdgcn_rcpf(dd) : 1.f;
               W = valid ? W : 0.f;
               stat += W * W;
               o = W * s;
@@ -667,7 +655,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           }
         }
       }
-      stat = wave_sum_f(stat);
+      stat = wave_sum_uniform(stat);
       if (STEP == 1 && d.nkept && l == 0) d.nkept[(size_t)ch * d.nr * d.nc + r] = (int32_t)stat;
       wgt = STEP == 1 ? (stat >= 1.f ? 1.f / stat : 1.f) : (stat > 0.f ? 1.f / stat : 1.f);
     }
@@ -683,13 +671,12 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
         for (int tt = 0; tt < 2; tt++) {
           if (tt >= NG) break;
-          acc = XF::mma(XF::cvt(D2[tt][ct]), had_frag<XF>(gt, tt, n), acc);
+          acc = XF::mma(XF::cvt(D2[tt][ct]), Hf[gt][tt], acc);
         }
         D3[ct][gt] = acc * rsn;
       }
     }
     // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
-    const int ru = l >> 3, rv = l & 7;
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) {
       if (gt >= NG) break;
@@ -704,37 +691,37 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         f32x4 add;
 #pragma unroll
         for (int v = 0; v < 4; v++) add[v] = wgt * Ku[mt] * Kv[v] * (acc[v] + centre);
-        *(f32x4*)(wst + col * 64 + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
+        *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
       }
       if (q == 0 && mv[gt]) {
         float* pw = wW + (my[gt] - g.uy0) * WW + (mx[gt] - g.ux0);
         *pw = *pw + wgt;
       }
       wave_lds_sync();
+      // four members per step; a missing member goes to the lane's spare slot
       const int packed = mv[gt] ? (((my[gt] - g.uy0) << 16) | (mx[gt] - g.ux0)) : -1;
       for (int mb = 0; mb < 16; mb += 4) {
         if (16 * gt + mb >= n) break;
         int a[4];
         float sv[4], o[4];
-        bool ok[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int pk = __builtin_amdgcn_readlane(packed, mb + i);
-          ok[i] = pk >= 0;
           const int py = pk >> 16, px = pk & 0xffff;
           const int u = (ru - py) & 7, v = (rv - px) & 7;
-          a[i] = ok[i] ? (py + u) * RP + px + v : 0;
-          sv[i] = ok[i] ? wst[(mb + i) * 64 + u * 8 + v] : 0.f;
+          a[i] = pk >= 0 ? (py + u) * RP + px + v : spare;
+          sv[i] = wst[(mb + i) * C::kSP + u * 8 + v];
+          sv[i] = pk >= 0 ? sv[i] : 0.f;
         }
 #pragma unroll
-        for (int i = 0; i < 4; i++) o[i] = ok[i] ? wnum[a[i]] : 0.f;
+        for (int i = 0; i < 4; i++) o[i] = wnum[a[i]];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           float t = o[i] + sv[i];
 #pragma unroll
-          for (int j = 0; j < 4; j++)
-            if (j != i && ok[j] && a[j] == a[i]) t += sv[j];
-          if (ok[i]) wnum[a[i]] = t;
+          for (int k = 0; k < 4; k++)
+            if (k != i) t += a[k] == a[i] ? sv[k] : 0.f;
+          wnum[a[i]] = t;
         }
       }
       wave_lds_sync();
