@@ -469,10 +469,8 @@ __device__ inline typename XF::frag had_frag(int rt, int kt, int n) {
   const int l = lane_id();
   const int row = 16 * rt + (l & 15), k0 = 16 * kt + 4 * (l >> 4);
   f32x4 a;
-  a[0] = had(row, k0, n);
-  a[1] = had(row, k0 + 1, n);
-  a[2] = had(row, k0 + 2, n);
-  a[3] = had(row, k0 + 3, n);
+#pragma unroll
+  for (int v = 0; v < 4; v++) a[v] = had(row, k0 + v, n);
   return XF::cvt(a);
 }
 
@@ -525,7 +523,6 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const int RP = C::pitch(RW);             // its row pitch
   const int WW = g.nx;                     // weight map row pitch (positions)
   float* wst = wW + C::rw(S, T) * C::rw(S, T);  // staging [16][kSP]
-  const int spare = (int)(wst + 16 * C::kSP - wnum) + l;  // this lane's spare slot
 
   for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
   for (int i = l; i < g.ny * WW; i += 64) wW[i] = 0.f;
@@ -536,14 +533,28 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const float* __restrict__ basic = d.basic + ch * hw;
   const float sig2 = d.sigma * d.sigma;
   const float thr = d.lam_sigma;
+  const float inv_w = 1.f / (float)w;
+  // Kaiser weight of the pixels this lane holds in an inverse-DCT
+  // fragment: Ku[mt] (row factor) times Kv[v] (column factor)
   float Ku[4], Kv[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
     Ku[i] = kp.kaiser[2 * i + (q >> 1)];
     Kv[i] = kp.kaiser[4 * (q & 1) + i];
   }
+  // the lane owns accumulator residue (ru, rv); for a patch whose corner has
+  // phase s (mod 8) the owned pixel sits at patch row (ru - s) & 7, packed
+  // here in 3-bit fields for s = 0..7 (same for columns)
   const int ru = l >> 3, rv = l & 7;
+  uint32_t Upk = 0, Vpk = 0;
+#pragma unroll
+  for (int s = 0; s < 8; s++) {
+    Upk |= (uint32_t)((ru - s) & 7) << (3 * s);
+    Vpk |= (uint32_t)((rv - s) & 7) << (3 * s);
+  }
 
+  frag Hf[2][2];  // Hadamard blocks of the current group size
+  int hn = 0;
   const int nrefs = g.nri * g.nci;
   for (int j = 0; j < nrefs; j++) {
     const int ri = g.ri0 + j / g.nci, ci = g.ci0 + j % g.nci;
@@ -560,27 +571,34 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       int gm = 16 * gt + col;
       mv[gt] = gt < NG && gm < n;
       int gi = ldg(idx + r * nmax + (mv[gt] ? gm : 0));
-      int yy = gi >= 0 ? gi / w : -1, xx = gi >= 0 ? gi - yy * w : -1;
+      // gi / w through a float reciprocal, corrected by one either way
+      int yy = (int)((float)gi * inv_w), xx = gi - yy * w;
+      yy = xx < 0 ? yy - 1 : xx >= w ? yy + 1 : yy;
+      xx = gi - yy * w;
       // a member must lie in the tile's search region (true for any grouping
       // made with the same window rule); anything else is ignored
-      bool inside = yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
+      bool inside = gi >= 0 && yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
       mv[gt] = mv[gt] && inside;
       my[gt] = inside ? yy : g.uy0;
       mx[gt] = inside ? xx : g.ux0;
     }
-    // Hadamard fragments: Hf[a][b] holds block (a, b) of the n-point matrix
-    // (symmetric, so it serves as both A and B operand)
-    frag Hf[2][2];
+    // members 0..n-1 all present (the normal case)?
+    const uint32_t vm = (uint32_t)(__ballot(mv[0]) & 0xffffu) | ((uint32_t)(__ballot(mv[1]) & 0xffffu) << 16);
+    const bool all_present = vm == (n == 32 ? ~0u : (1u << n) - 1u);
+    if (n != hn) {
+      hn = n;
 #pragma unroll
-    for (int a = 0; a < 2; a++)
+      for (int a = 0; a < 2; a++)
 #pragma unroll
-      for (int b = 0; b < 2; b++) Hf[a][b] = had_frag<XF>(a, b, n);
+        for (int b = 0; b < 2; b++) Hf[a][b] = had_frag<XF>(a, b, n);
+    }
 
     // ---- forward: 2-D DCT then WHT of the noisy (and in step 2 the basic) group
     f32x4 D2[2][4], D2b[2][4];
 #pragma unroll
     for (int src_i = 0; src_i < (STEP == 2 ? 2 : 1); src_i++) {
       const float* __restrict__ src0 = src_i == 0 ? noisy : basic;
+      __builtin_amdgcn_sched_barrier(0);  // one group's loads in flight at a time
       f32x4 D1[2][4];
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
@@ -592,14 +610,17 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
           for (int v = 0; v < 4; v++) a[kt][v] = ldg(src + v);  // always a valid pixel
         }
+        if (!all_present) {  // an absent member enters as a zero patch
+#pragma unroll
+          for (int kt = 0; kt < 4; kt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) a[kt][v] = mv[gt] ? a[kt][v] : centre;
+        }
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
 #pragma unroll
         for (int kt = 0; kt < 4; kt++) {
-          f32x4 c;
-#pragma unroll
-          for (int v = 0; v < 4; v++) c[v] = mv[gt] ? a[kt][v] - centre : 0.f;
-          frag af = XF::cvt(c);
+          frag af = XF::cvt(a[kt] - centre);
 #pragma unroll
           for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
         }
@@ -621,46 +642,75 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       }
     }
 
-    // ---- shrinkage; the centre only moves the 3-D DC, restored here
+    // ---- shrinkage.  Spectra rows t >= n are exactly zero (the Hadamard
+    // blocks vanish there), so they are never kept and get zero gain unless
+    // sigma = 0.  The centre only moves the 3-D DC, restored around this.
     const float off = 8.f * centre * sqrtf((float)n);
+    if (l == 0) {
+      D2[0][0][0] += off;
+      if (STEP == 2) D2b[0][0][0] += off;
+    }
     float wgt;
-    {
-      float stat = 0.f;
+    if (STEP == 1) {
+      int kept = 0;
 #pragma unroll
       for (int tt = 0; tt < 2; tt++) {
         if (tt >= NG) break;
 #pragma unroll
-        for (int nt = 0; nt < 4; nt++) {
+        for (int nt = 0; nt < 4; nt++)
 #pragma unroll
           for (int v = 0; v < 4; v++) {
-            const int t = 16 * tt + 4 * q + v;
-            const bool valid = t < n;
-            const bool isdc = tt == 0 && nt == 0 && l == 0 && v == 0;
-            float s = D2[tt][nt][v] + (isdc ? off : 0.f);
-            float o;
-            if (STEP == 1) {
-              bool keep = valid && fabsf(s) > thr;
-              stat += keep ? 1.f : 0.f;
-              o = keep ? s : 0.f;
-            } else {
-              float sb = D2b[tt][nt][v] + (isdc ? off : 0.f);
-              float b2 = sb * sb;
-              float dd = b2 + sig2;
-              float W = dd > 0.f ? b2 * __builtin_amdgcn_rcpf(dd) : 1.f;
-              W = valid ? W : 0.f;
-              stat += W * W;
-              o = W * s;
-            }
-            D2[tt][nt][v] = isdc ? o - off : o;
+            const bool keep = fabsf(D2[tt][nt][v]) > thr;
+            kept += __popcll(__ballot(keep));
+            D2[tt][nt][v] = keep ? D2[tt][nt][v] : 0.f;
           }
+      }
+      if (d.nkept && l == 0) d.nkept[(size_t)ch * d.nr * d.nc + r] = kept;
+      wgt = kept >= 1 ? 1.f / (float)kept : 1.f;
+    } else {
+      float sw2 = 0.f;
+      if (sig2 > 0.f) {
+#pragma unroll
+        for (int tt = 0; tt < 2; tt++) {
+          if (tt >= NG) break;
+#pragma unroll
+          for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+              const float b2 = D2b[tt][nt][v] * D2b[tt][nt][v];
+              const float W = b2 * __builtin_amdgcn_rcpf(b2 + sig2);
+              sw2 += W * W;
+              D2[tt][nt][v] *= W;
+            }
+        }
+      } else {  // sigma = 0: W = 1 wherever B = 0, inside the group only
+#pragma unroll
+        for (int tt = 0; tt < 2; tt++) {
+          if (tt >= NG) break;
+#pragma unroll
+          for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+              const float b2 = D2b[tt][nt][v] * D2b[tt][nt][v];
+              float W = b2 > 0.f ? 1.f : 0.f;
+              W = 16 * tt + 4 * q + v < n ? W + (1.f - W) : 0.f;
+              sw2 += W * W;
+              D2[tt][nt][v] *= W;
+            }
         }
       }
-      stat = wave_sum_uniform(stat);
-      if (STEP == 1 && d.nkept && l == 0) d.nkept[(size_t)ch * d.nr * d.nc + r] = (int32_t)stat;
-      wgt = STEP == 1 ? (stat >= 1.f ? 1.f / stat : 1.f) : (stat > 0.f ? 1.f / stat : 1.f);
+      sw2 = wave_sum_uniform(sw2);
+      wgt = sw2 > 0.f ? 1.f / sw2 : 1.f;
     }
+    if (l == 0) D2[0][0][0] -= off;
 
-    // ---- inverse WHT
+    // ---- inverse WHT, with this lane's member weight (0 if absent) folded in
+    float wm[2], cw[2];
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      wm[gt] = mv[gt] ? wgt : 0.f;
+      cw[gt] = wm[gt] * centre;
+    }
     f32x4 D3[4][2];
 #pragma unroll
     for (int ct = 0; ct < 4; ct++) {
@@ -673,7 +723,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           if (tt >= NG) break;
           acc = XF::mma(XF::cvt(D2[tt][ct]), Hf[gt][tt], acc);
         }
-        D3[ct][gt] = acc * rsn;
+        D3[ct][gt] = acc * (rsn * wm[gt]);
       }
     }
     // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
@@ -690,7 +740,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int ct = 0; ct < 4; ct++) acc = XF::mma(tabA[(mt * 4 + ct) * 64 + l], b3[ct], acc);
         f32x4 add;
 #pragma unroll
-        for (int v = 0; v < 4; v++) add[v] = wgt * Ku[mt] * Kv[v] * (acc[v] + centre);
+        for (int v = 0; v < 4; v++) add[v] = (Ku[mt] * Kv[v]) * (acc[v] + cw[gt]);
         *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
       }
       if (q == 0 && mv[gt]) {
@@ -698,8 +748,11 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         *pw = *pw + wgt;
       }
       wave_lds_sync();
-      // four members per step; a missing member goes to the lane's spare slot
-      const int packed = mv[gt] ? (((my[gt] - g.uy0) << 16) | (mx[gt] - g.ux0)) : -1;
+      // four members per step (an absent member stages zeros at the region
+      // corner); the writes go in member order, so where members coincide
+      // on this lane's pixel the last write carries every contribution
+      const int packed = mv[gt] ? (((my[gt] - g.uy0) << 16) | (mx[gt] - g.ux0)) : 0;
+#pragma unroll
       for (int mb = 0; mb < 16; mb += 4) {
         if (16 * gt + mb >= n) break;
         int a[4];
@@ -708,10 +761,9 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int i = 0; i < 4; i++) {
           const int pk = __builtin_amdgcn_readlane(packed, mb + i);
           const int py = pk >> 16, px = pk & 0xffff;
-          const int u = (ru - py) & 7, v = (rv - px) & 7;
-          a[i] = pk >= 0 ? (py + u) * RP + px + v : spare;
+          const int u = (Upk >> (3 * (py & 7))) & 7, v = (Vpk >> (3 * (px & 7))) & 7;
+          a[i] = u * RP + v + (py * RP + px);
           sv[i] = wst[(mb + i) * C::kSP + u * 8 + v];
-          sv[i] = pk >= 0 ? sv[i] : 0.f;
         }
 #pragma unroll
         for (int i = 0; i < 4; i++) o[i] = wnum[a[i]];
@@ -719,8 +771,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int i = 0; i < 4; i++) {
           float t = o[i] + sv[i];
 #pragma unroll
-          for (int k = 0; k < 4; k++)
-            if (k != i) t += a[k] == a[i] ? sv[k] : 0.f;
+          for (int k = 0; k < i; k++) t += a[k] == a[i] ? sv[k] : 0.f;
           wnum[a[i]] = t;
         }
       }
