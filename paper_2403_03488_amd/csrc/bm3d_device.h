@@ -86,60 +86,105 @@ __device__ inline uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-__device__ inline uint32_t shfl_xor_u32(uint32_t v, int m) { return (uint32_t)__shfl_xor((int)v, m); }
-__device__ inline uint32_t shfl_u32(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
-  uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
-  return ((uint64_t)hi << 32) | lo;
+// Cross-lane moves in registers only (no LDS traffic): DPP within rows of 16
+// lanes, the gfx950 row-swap instructions across rows.  Lane-select masks
+// are constants turned into per-lane conditions with inverse_ballot.
+template <int CTRL> __device__ inline uint32_t dpp_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
 }
-__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
-  uint32_t lo = shfl_u32((uint32_t)v, src), hi = shfl_u32((uint32_t)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
+__device__ inline bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
+// value held by lane l ^ J
+template <int J> __device__ inline uint32_t xor_lane(uint32_t v) {
+  if constexpr (J == 1) {
+    return dpp_u<0xB1>(v);  // quad_perm [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return dpp_u<0x4E>(v);  // quad_perm [2,3,0,1]
+  } else if constexpr (J == 4) {  // row_ror 4 brings lane l-4, row_ror 12 lane l+4
+    // both moves run on every lane (a move under a partial exec mask would
+    // read inactive lanes), then each lane picks its partner
+    const uint32_t a = dpp_u<0x124>(v), b = dpp_u<0x12C>(v);
+    return lane_in(0xF0F0F0F0F0F0F0F0ull) ? a : b;
+  } else if constexpr (J == 8) {
+    return dpp_u<0x128>(v);  // row_ror 8
+  } else if constexpr (J == 16) {  // rows 2i, 2i+1 exchanged
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    const uint32_t a = r[0], b = r[1];
+    return lane_in(0xFFFF0000FFFF0000ull) ? a : b;
+  } else {
+    static_assert(J == 32, "lane distance");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    const uint32_t a = r[0], b = r[1];
+    return lane_in(0xFFFFFFFF00000000ull) ? a : b;
+  }
 }
-template <class K> __device__ inline K shfl_xor_k(K v, int m);
-template <> __device__ inline uint32_t shfl_xor_k<uint32_t>(uint32_t v, int m) { return shfl_xor_u32(v, m); }
-template <> __device__ inline uint64_t shfl_xor_k<uint64_t>(uint64_t v, int m) { return shfl_xor_u64(v, m); }
-template <class K> __device__ inline K shfl_k(K v, int s);
-template <> __device__ inline uint32_t shfl_k<uint32_t>(uint32_t v, int s) { return shfl_u32(v, s); }
-template <> __device__ inline uint64_t shfl_k<uint64_t>(uint64_t v, int s) { return shfl_u64(v, s); }
+template <class K, int J> __device__ inline K xor_lane_k(K v) {
+  if constexpr (sizeof(K) == 4) {
+    return (K)xor_lane<J>((uint32_t)v);
+  } else {
+    uint32_t lo = xor_lane<J>((uint32_t)v), hi = xor_lane<J>((uint32_t)(v >> 32));
+    return ((K)hi << 32) | lo;
+  }
+}
+// value held by lane 63 - l
+template <class K> __device__ inline K reverse_lanes(K v) {
+  if constexpr (sizeof(K) == 4) {
+    uint32_t m = dpp_u<0x140>((uint32_t)v);  // row_mirror: 16i + 15 - r
+    return (K)xor_lane<16>(xor_lane<32>(m));
+  } else {
+    return ((K)reverse_lanes<uint32_t>((uint32_t)(v >> 32)) << 32) | reverse_lanes<uint32_t>((uint32_t)v);
+  }
+}
+template <class K> __device__ inline K lane_value(K v, int src) {  // src wave-uniform
+  if constexpr (sizeof(K) == 4) {
+    return (K)__builtin_amdgcn_readlane((int)v, src);
+  } else {
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((K)hi << 32) | lo;
+  }
+}
 
 template <class K> __device__ inline K kmin(K a, K b) { return a < b ? a : b; }
 template <class K> __device__ inline K kmax(K a, K b) { return a < b ? b : a; }
 
-// Bitonic sort of one key per lane across the wave, ascending by lane.
-template <class K> __device__ inline K wave_sort(K v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      K o = shfl_xor_k<K>(v, j);
-      bool up = (l & k) == 0;
-      bool lower = (l & j) == 0;
-      v = (lower == up) ? kmin(v, o) : kmax(v, o);
-    }
-  }
+// Lanes that keep the smaller key in bitonic step (block KB, distance J).
+constexpr uint64_t bitonic_min_lanes(int KB, int J) {
+  uint64_t m = 0;
+  for (int l = 0; l < 64; l++)
+    if (((l & J) == 0) == ((l & KB) == 0)) m |= 1ull << l;
+  return m;
+}
+// one compare-exchange step at lane distance J; lanes in MINL keep the minimum
+template <class K, int J, uint64_t MINL> __device__ inline K cmp_xchg(K v) {
+  const K o = xor_lane_k<K, J>(v);
+  const bool keep = (v < o) == lane_in(MINL);
+  return keep ? v : o;
+}
+template <class K, int KB, int J> __device__ inline K bitonic_steps(K v) {
+  v = cmp_xchg<K, J, bitonic_min_lanes(KB, J)>(v);
+  if constexpr (J > 1) v = bitonic_steps<K, KB, J / 2>(v);
   return v;
 }
+template <class K, int KB> __device__ inline K bitonic_stages(K v) {
+  v = bitonic_steps<K, KB, KB / 2>(v);
+  if constexpr (KB < 64) v = bitonic_stages<K, KB * 2>(v);
+  return v;
+}
+// Bitonic sort of one key per lane across the wave, ascending by lane.
+template <class K> __device__ inline K wave_sort(K v) { return bitonic_stages<K, 2>(v); }
 
 // a, b ascending across lanes -> the 64 smallest of a U b, ascending.
-template <class K> __device__ inline K wave_merge_low(K a, K b) {
-  const int l = lane_id();
-  K m = kmin(a, shfl_k<K>(b, 63 - l));
-#pragma unroll
-  for (int j = 32; j > 0; j >>= 1) {
-    K o = shfl_xor_k<K>(m, j);
-    m = (l & j) ? kmax(m, o) : kmin(m, o);
-  }
+template <class K, int J> __device__ inline K half_clean(K m) {
+  m = cmp_xchg<K, J, bitonic_min_lanes(64, J)>(m);
+  if constexpr (J > 1) m = half_clean<K, J / 2>(m);
   return m;
+}
+template <class K> __device__ inline K wave_merge_low(K a, K b) {
+  return half_clean<K, 32>(kmin(a, reverse_lanes<K>(b)));
 }
 
 __device__ inline int wave_sum_i(int v) {
-#pragma unroll
-  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
-  return v;
-}
-__device__ inline float wave_sum_f(float v) {
 #pragma unroll
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
   return v;
@@ -192,7 +237,7 @@ __device__ int select_group(const K (&k)[16], int nmax, K* buf, K& sel) {
   K mn = k[0];
 #pragma unroll
   for (int t = 1; t < 16; t++) mn = kmin(mn, k[t]);
-  K theta = shfl_k<K>(wave_sort(mn), want - 1);
+  K theta = lane_value<K>(wave_sort(mn), want - 1);
   // compact the survivors (candidates with key <= theta) into buf
   int base = 0;
   const uint64_t lt = lanemask_lt();
