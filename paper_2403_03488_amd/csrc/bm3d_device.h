@@ -270,6 +270,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
+// mma2 contracts over two 16-deep tiles at once (a0.b0 + a1.b1).  The
+// 32-deep instructions take 8 values per lane; pairing the two tiles' values
+// in the same slots of both operands gives the same sum whatever order the
+// hardware assigns to the 32 contraction indices.
 struct XF32 {
   typedef f32x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return a; }
@@ -280,6 +284,9 @@ struct XF32 {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
     return c;
   }
+  static __device__ inline f32x4 mma2(frag a0, frag a1, frag b0, frag b1, f32x4 c) {
+    return mma(a1, b1, mma(a0, b0, c));
+  }
 };
 struct XBF16 {
   typedef bf16x4 frag;
@@ -287,12 +294,24 @@ struct XBF16 {
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
+  static __device__ inline f32x4 mma2(frag a0, frag a1, frag b0, frag b1, f32x4 c) {
+    typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+    const bf16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
 };
 struct XF16 {
   typedef f16x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline f32x4 mma2(frag a0, frag a1, frag b0, frag b1, f32x4 c) {
+    typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+    const f16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const f16x8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
 };
 

@@ -499,7 +499,12 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
       }
       v4[v] = Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
     }
-    (tab == 0 ? tabB : tabA)[f * 64 + ln] = XF::cvt(v4);
+    // stored so that the two tiles of one 32-deep contraction step are
+    // adjacent for each lane: B at ((kt/2)*4 + nt, lane, kt%2), A at
+    // (mt*2 + ct/2, lane, ct%2)
+    const int pair = tab == 0 ? ((f >> 3) * 4 + (f & 3)) : ((f >> 2) * 2 + ((f & 3) >> 1));
+    const int half = tab == 0 ? ((f >> 2) & 1) : (f & 1);
+    (tab == 0 ? tabB : tabA)[(pair * 64 + ln) * 2 + half] = XF::cvt(v4);
   }
 }
 
@@ -619,10 +624,13 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++) {
-          frag af = XF::cvt(a[kt] - centre);
+        for (int k2 = 0; k2 < 2; k2++) {
+          const frag a0 = XF::cvt(a[2 * k2] - centre), a1 = XF::cvt(a[2 * k2 + 1] - centre);
 #pragma unroll
-          for (int nt = 0; nt < 4; nt++) D1[gt][nt] = XF::mma(af, tabB[(kt * 4 + nt) * 64 + l], D1[gt][nt]);
+          for (int nt = 0; nt < 4; nt++) {
+            const frag* tb = tabB + ((k2 * 4 + nt) * 64 + l) * 2;
+            D1[gt][nt] = XF::mma2(a0, a1, tb[0], tb[1], D1[gt][nt]);
+          }
         }
       }
 #pragma unroll
@@ -630,12 +638,8 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         if (tt >= NG) break;
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) {
-          f32x4 acc = zero4();
-#pragma unroll
-          for (int gt = 0; gt < 2; gt++) {
-            if (gt >= NG) break;
-            acc = XF::mma(Hf[tt][gt], XF::cvt(D1[gt][nt]), acc);
-          }
+          const f32x4 acc = NG == 2 ? XF::mma2(Hf[tt][0], Hf[tt][1], XF::cvt(D1[0][nt]), XF::cvt(D1[1][nt]), zero4())
+                                    : XF::mma(Hf[tt][0], XF::cvt(D1[0][nt]), zero4());
           if (src_i == 0) D2[tt][nt] = acc * rsn;
           else D2b[tt][nt] = acc * rsn;
         }
@@ -717,12 +721,8 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
-        f32x4 acc = zero4();
-#pragma unroll
-        for (int tt = 0; tt < 2; tt++) {
-          if (tt >= NG) break;
-          acc = XF::mma(XF::cvt(D2[tt][ct]), Hf[gt][tt], acc);
-        }
+        const f32x4 acc = NG == 2 ? XF::mma2(XF::cvt(D2[0][ct]), XF::cvt(D2[1][ct]), Hf[gt][0], Hf[gt][1], zero4())
+                                  : XF::mma(XF::cvt(D2[0][ct]), Hf[gt][0], zero4());
         D3[ct][gt] = acc * (rsn * wm[gt]);
       }
     }
@@ -737,7 +737,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       for (int mt = 0; mt < 4; mt++) {
         f32x4 acc = zero4();
 #pragma unroll
-        for (int ct = 0; ct < 4; ct++) acc = XF::mma(tabA[(mt * 4 + ct) * 64 + l], b3[ct], acc);
+        for (int c2 = 0; c2 < 2; c2++) {
+          const frag* ta = tabA + ((mt * 2 + c2) * 64 + l) * 2;
+          acc = XF::mma2(ta[0], ta[1], b3[2 * c2], b3[2 * c2 + 1], acc);
+        }
         f32x4 add;
 #pragma unroll
         for (int v = 0; v < 4; v++) add[v] = (Ku[mt] * Kv[v]) * (acc[v] + cw[gt]);
@@ -762,7 +765,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           const int pk = __builtin_amdgcn_readlane(packed, mb + i);
           const int py = pk >> 16, px = pk & 0xffff;
           const int u = (Upk >> (3 * (py & 7))) & 7, v = (Vpk >> (3 * (px & 7))) & 7;
-          a[i] = u * RP + v + (py * RP + px);
+          a[i] = (int)__umul24((unsigned)u, (unsigned)RP) + v + (py * RP + px);
           sv[i] = wst[(mb + i) * C::kSP + u * 8 + v];
         }
 #pragma unroll
