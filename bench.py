@@ -58,10 +58,10 @@ def work_models(h, w, S, cnt1, cnt2, c=1):
     }
 
 
-def measured_traffic(kernel, images):
+def measured_traffic(kernel, images, tile):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/hbm_traffic_*.json), if they were taken on the current kernel
-    sources; None otherwise."""
+    sources with the same filter tile; None otherwise."""
     import glob
     import hashlib
     src = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(
@@ -69,7 +69,8 @@ def measured_traffic(kernel, images):
     sha = hashlib.sha256(src.encode()).hexdigest()[:16]
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
         rec = json.load(open(path))
-        if rec.get("source_sha") == sha and kernel in rec.get("kernels", {}):
+        if (rec.get("source_sha") == sha and rec.get("tile_refs") == tile
+                and kernel in rec.get("kernels", {})):
             k = rec["kernels"][kernel]
             return images * (k["fetch_bytes_per_image"] + k["write_bytes_per_image"])
     return None
@@ -113,6 +114,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="force the filter tile side (refs)")
+    ap.add_argument("--persistent", type=int, default=-1, help="force workgroups per CU (0 = one per item)")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -137,11 +140,15 @@ def main():
     outs = [torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(B)]
 
     p = bm3d.params_default(sigma, xform=XF[args.xform])
-    if not args.no_autotune:
+    if not args.no_autotune and not (args.tile and args.persistent >= 0):
         t0 = time.time()
         p = bm3d.autotune(p, None)
         log("autotune: tile %d refs, persistent %d WG/CU (%.1fs)" % (p.tile_refs, p.persistent_wgs,
                                                                      time.time() - t0))
+    if args.tile:
+        p.tile_refs = args.tile
+    if args.persistent >= 0:
+        p.persistent_wgs = args.persistent
     plan = bm3d.Batch(imgs, outs, [sigma] * B, p)
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
     torch.cuda.set_stream(stream)
@@ -213,7 +220,7 @@ def main():
     achieved = work[dom] / (stage_ms[dom] * 1e-3)
     roof = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic(dom, B) if args.xform == "bf16" else None,
+            "traffic": measured_traffic(dom, B, p.tile_refs) if args.xform == "bf16" else None,
             "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom]}
     per_stage = {k: {"ms": stage_ms[k], "frac": (work[k] / (stage_ms[k] * 1e-3)) / kinds[k][2]}
                  for k in work}
