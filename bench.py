@@ -104,6 +104,155 @@ def single_image_checks(torch, bm3d, synth, p, imgs, outs, samples, sigma, H, W,
     return lat_ms, fp32_single, psnr32, psnrlo
 
 
+def stage_times(torch, bm3d, plan, B, stream):
+    """Per-stage kernel time (ms) with HIP events on the launch stream.  After
+    one full pass the matching/filter stages can be re-run on valid data (the
+    filters only add into num/den); the stages that reset or rewrite state
+    (prep + zero-fill, agg1 + zero-fill, agg2) are timed last."""
+    plan.run(stream)
+    stage_ms = {}
+    for st in (1, 2, 4, 5, 0, 3, 6):
+        name = bm3d.STAGES[st]
+        reps = 5
+        plan.run_stages(0, B, st, st, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.run_stages(0, B, st, st, stream)
+        e1.record(stream)
+        e1.synchronize()
+        stage_ms[name] = e0.elapsed_time(e1) / reps
+    return stage_ms
+
+
+def tuned_params(args, bm3d, sigma, flags=0):
+    p = bm3d.params_default(sigma, xform=XF[args.xform], flags=flags)
+    if not args.no_autotune and not (args.tile and args.persistent >= 0):
+        t0 = time.time()
+        q = bm3d.autotune(p, None)
+        p.tile_refs, p.persistent_wgs = q.tile_refs, q.persistent_wgs
+        log("autotune: tile %d refs, persistent %d WG/CU (%.1fs)" % (p.tile_refs, p.persistent_wgs,
+                                                                     time.time() - t0))
+    if args.tile:
+        p.tile_refs = args.tile
+    if args.persistent >= 0:
+        p.persistent_wgs = args.persistent
+    return p
+
+
+def run_batch64(args):
+    """The mixed batch: 64 images of areas 128^2..1024^2 (aspect 1:1-2:1),
+    half grey / half colour, sigma ~ U[10,50], one captured graph per step."""
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+    assert torch.cuda.is_available(), "no GPU"
+    shapes = synth.batch_shapes(64)
+    log("generating the 64-image mixed batch")
+    samples = [synth.batch_image(i, sh) for i, sh in enumerate(shapes)]
+    imgs = [torch.from_numpy(s.noisy).cuda() for s in samples]
+    outs = [torch.empty(s.noisy.shape, dtype=torch.float32, device="cuda") for s in samples]
+    p = tuned_params(args, bm3d, 25.0, bm3d.FLAG_SIGMA_PROFILE)
+    plan = bm3d.Batch(imgs, outs, [s.sigma for s in samples], p)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    torch.cuda.synchronize()
+    plan.capture(stream)
+    for _ in range(args.warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    mp = sum(s.h * s.w for s in samples) / 1e6
+    cmp = sum(s.h * s.w * s.c for s in samples) / 1e6
+    log("mixed batch %s: %.3f ms/step, %.1f MP/s" % (args.xform, dt * 1e3, mp / dt))
+    stage_ms = stage_times(torch, bm3d, plan, len(samples), stream)
+    plan.launch(stream)
+    torch.cuda.synchronize()
+    ps = [synth.psnr(s.clean, o.cpu().numpy()) for s, o in zip(samples, outs)]
+    res = {
+        "metric": "denoised MP/s (64-image mixed batch, both BM3D steps)", "value": mp / dt,
+        "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.xform + "+int8", "data": "synthetic",
+        "config": {"workload": "64 images, areas 128^2-1024^2, aspect 1:1-2:1, half grey / half colour, "
+                               "sigma U[10,50], one graph-captured batched pass per step",
+                   "megapixels": mp, "channel_megapixels": cmp, "xform": args.xform,
+                   "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs},
+        "channel_MPps": cmp / dt, "stages_ms": stage_ms,
+        "psnr_db": {"mean": float(np.mean(ps)), "min": float(np.min(ps))},
+    }
+    print(json.dumps(res), flush=True)
+    plan.close()
+
+
+def run_serving(args):
+    """Serving: Poisson arrivals at 0.7x the measured batched capacity, sides
+    log-uniform 256-4096, 70 % grey, sigma U[5,60], 30 % moire.  The request
+    loop (stage-level continuous batching, BF16 transforms + int8 matching)
+    against the plain FP32 single-image path serving the same trace one
+    request at a time."""
+    import torch
+    from paper_2403_03488_amd import bm3d, serve, synth
+    assert torch.cuda.is_available(), "no GPU"
+    n = args.requests
+    log("building %d serving requests (canvases, noise, pinned inputs)" % n)
+    canv = synth.serving_canvases(4096)
+    noise = synth.serving_noise(4096)
+    specs = synth.serving_specs(n, rate=1.0)  # arrival times in units of 1/rate
+    hosts = []
+    for sp in specs:
+        x = torch.from_numpy(synth.crop_clean(canv, sp)).float()
+        x.add_(torch.from_numpy(synth.noise_crop(noise, sp)), alpha=sp["sigma"]).round_().clamp_(0, 255)
+        buf = torch.empty(x.shape, dtype=torch.uint8, pin_memory=True)
+        buf.copy_(x)
+        hosts.append(buf)
+    del canv, noise
+    mean_mp = sum(sp["h"] * sp["w"] for sp in specs) / 1e6 / n
+    log("requests ready: mean %.2f MP" % mean_mp)
+    p = tuned_params(args, bm3d, 25.0, bm3d.FLAG_SIGMA_PROFILE)
+    p32 = bm3d.params_default(25.0, xform=0, flags=bm3d.FLAG_SIGMA_PROFILE)
+
+    def requests(scale):
+        return [serve.Request(sp["rid"], sp["arrival"] * scale, h, sp["sigma"]) for sp, h in zip(specs, hosts)]
+
+    # warm-up and capacity: the first requests all present at t = 0
+    m = min(n, args.capacity_requests)
+    serve.ServingLoop(p, max_slots=args.slots).run(requests(0.0)[:8])
+    torch.cuda.synchronize()
+    cap = serve.summarize(serve.ServingLoop(p, max_slots=args.slots).run(requests(0.0)[:m]))
+    cap_req = cap["MPps"] / mean_mp
+    rate = args.load * cap_req
+    log("capacity %.1f MP/s (%.1f req/s); offered load %.2f -> %.2f req/s" % (cap["MPps"], cap_req,
+                                                                            args.load, rate))
+    loop = serve.ServingLoop(p, max_slots=args.slots)
+    rs = loop.run(requests(1.0 / rate))
+    st = serve.summarize(rs)
+    log("served: %.1f MP/s, p50 %.1f ms, p99 %.1f ms, %d ticks (mean %.1f requests per tick)" % (
+        st["MPps"], st["p50_ms"], st["p99_ms"], loop.ticks, np.mean(loop.tick_sizes)))
+    base = serve.summarize(serve.serve_one_at_a_time(requests(1.0 / rate), p32))
+    log("FP32 single-image path: %.1f MP/s, p50 %.1f ms, p99 %.1f ms" % (base["MPps"], base["p50_ms"],
+                                                                        base["p99_ms"]))
+    res = {
+        "metric": "served MP/s with p50/p99 latency (Poisson arrivals at %.1fx capacity)" % args.load,
+        "value": st["MPps"], "unit": "MP/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": args.xform + "+int8", "data": "synthetic",
+        "config": {"workload": "serving: %d requests, sides log-uniform 256-4096, 70%% grey / 30%% colour, "
+                               "sigma U[5,60], 30%% moire, Poisson arrivals" % n,
+                   "requests": n, "mean_MP": mean_mp, "rate_req_s": rate, "slots": args.slots,
+                   "xform": args.xform, "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs},
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "makespan_s": st["makespan_s"], "capacity_MPps": cap["MPps"],
+        "ticks": loop.ticks, "mean_requests_per_tick": float(np.mean(loop.tick_sizes)),
+        "peak_hbm_bytes": loop.peak_used,
+        "fp32_single_image_path": {"MPps": base["MPps"], "p50_ms": base["p50_ms"],
+                                   "p99_ms": base["p99_ms"], "makespan_s": base["makespan_s"]},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +269,14 @@ def main():
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving"],
+                    help="grey512: the headline 16 x 512^2 batch (default); batch64: the 64-image "
+                         "mixed batch; serving: the request loop against the FP32 single-image path")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
+    ap.add_argument("--slots", type=int, default=32, help="serving: requests in flight")
+    ap.add_argument("--capacity-requests", type=int, default=300,
+                    help="serving: requests in the capacity measurement")
     args = ap.parse_args()
     if args.quick:
         args.no_autotune = args.no_cpu_baseline = True
@@ -127,6 +284,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the design notes for how the work would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        return run_batch64(args)
+    if args.workload == "serving":
+        return run_serving(args)
 
     import torch
     from paper_2403_03488_amd import bm3d, synth
@@ -139,16 +300,7 @@ def main():
     imgs = [torch.from_numpy(s.noisy).cuda() for s in samples]
     outs = [torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(B)]
 
-    p = bm3d.params_default(sigma, xform=XF[args.xform])
-    if not args.no_autotune and not (args.tile and args.persistent >= 0):
-        t0 = time.time()
-        p = bm3d.autotune(p, None)
-        log("autotune: tile %d refs, persistent %d WG/CU (%.1fs)" % (p.tile_refs, p.persistent_wgs,
-                                                                     time.time() - t0))
-    if args.tile:
-        p.tile_refs = args.tile
-    if args.persistent >= 0:
-        p.persistent_wgs = args.persistent
+    p = tuned_params(args, bm3d, sigma)
     plan = bm3d.Batch(imgs, outs, [sigma] * B, p)
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
     torch.cuda.set_stream(stream)
@@ -167,23 +319,7 @@ def main():
     value = mp / dt
     log("batched %s: %.3f ms/step, %.1f MP/s" % (args.xform, dt * 1e3, value))
 
-    # per-stage kernel time with HIP events on the launch stream.  After one
-    # full pass the matching/filter stages can be re-run on valid data (the
-    # filters only add into num/den); the stages that reset or rewrite state
-    # (prep + zero-fill, agg1 + zero-fill, agg2) are timed last.
-    plan.run(stream)
-    stage_ms = {}
-    for st in (1, 2, 4, 5, 0, 3, 6):
-        name = bm3d.STAGES[st]
-        reps = 5
-        plan.run_stages(0, B, st, st, stream)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            plan.run_stages(0, B, st, st, stream)
-        e1.record(stream)
-        e1.synchronize()
-        stage_ms[name] = e0.elapsed_time(e1) / reps
+    stage_ms = stage_times(torch, bm3d, plan, B, stream)
     log("stage ms: " + ", ".join("%s %.3f" % kv for kv in stage_ms.items()))
 
     # group sizes of every image (stage entry points, outside the timed region)

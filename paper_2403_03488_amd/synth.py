@@ -244,6 +244,23 @@ def serving_specs(n: int, rate: float, max_side: int = 4096, seed: int = 4001):
     return out
 
 
+def serving_noise(side: int = 4096, seed: int = 4002) -> np.ndarray:
+    """One seeded canvas of standard normals [side, side, 3] (float32); each
+    serving request takes its noise from a crop of it at its own offset."""
+    return np.random.default_rng(seed).standard_normal((side, side, 3), dtype=np.float32)
+
+
+def noise_crop(noise: np.ndarray, spec) -> np.ndarray:
+    """The request's noise: a crop of the noise canvas at an offset drawn
+    from its noise seed (shape HxW or HxWx3, float32)."""
+    r = np.random.default_rng(spec["noise_seed"])
+    side = noise.shape[0]
+    y0 = int(r.integers(0, side - spec["h"] + 1))
+    x0 = int(r.integers(0, side - spec["w"] + 1))
+    n = noise[y0:y0 + spec["h"], x0:x0 + spec["w"]]
+    return n[:, :, 0] if spec["c"] == 1 else n
+
+
 def crop_clean(canvases, spec):
     a = canvases[spec["kind"]]
     return np.ascontiguousarray(a[spec["y0"]:spec["y0"] + spec["h"], spec["x0"]:spec["x0"] + spec["w"]])
