@@ -234,27 +234,39 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
       A[3] = (int)(uint32_t)(r1 >> 32);
     }
   }
-  // accumulator rows 4q+v are references (row q, column v) of the block
-  int mwy[4], mwx[4], mry[4], mrx[4], mnp[4];
-  bool mval[4];
+  // accumulator rows 4q+v are references (row q, column v) of the block.
+  // The window origin row depends on the reference row only (q), the origin
+  // column on the reference column (v).  A candidate at union position
+  // (cy, cx) has window index widx = cy*SW + cx - (wy*SW + wx) and key slot
+  // (4q+v)*SS + widx.
+  const bool row_ok = q < g.nri;
+  int mwy;
+  {
+    int ry = ref_pos(g.ri0 + (row_ok ? q : 0), h), wy, t0;
+    window_1d(ry, h, S, wy, t0);
+    mwy = wy - g.uy0;
+  }
+  int mwx[4], wofs[4], slot[4], mnp[4];
 #pragma unroll
   for (int v = 0; v < 4; v++) {
-    mval[v] = q < g.nri && v < g.nci;
-    int ry = ref_pos(g.ri0 + (q < g.nri ? q : 0), h), rx = ref_pos(g.ci0 + (v < g.nci ? v : 0), w);
-    int wy, wx, t0;
-    window_1d(ry, h, S, wy, t0);
+    const bool ok = row_ok && v < g.nci;
+    int ry = ref_pos(g.ri0 + (row_ok ? q : 0), h), rx = ref_pos(g.ci0 + (v < g.nci ? v : 0), w);
+    int wx, t0;
     window_1d(rx, w, S, wx, t0);
-    mwy[v] = wy - g.uy0;
-    mwx[v] = wx - g.ux0;
-    mry[v] = ry - g.uy0;
-    mrx[v] = rx - g.ux0;
-    mnp[v] = nq[mry[v] * 48 + mrx[v]];
+    // an absent reference gets an origin no candidate column can reach
+    mwx[v] = ok ? wx - g.ux0 : -(1 << 20);
+    wofs[v] = -(mwy * SW + (wx - g.ux0));
+    slot[v] = (4 * q + v) * SS + wofs[v];
+    mnp[v] = nq[(ry - g.uy0) * 48 + (rx - g.ux0)];
   }
   const uint32_t thr = d.thr1;
-  const int ntile = g.ny * nblk;
-  for (int p = wave; p < ntile; p += nwaves) {
-    int cy = p / nblk, blk = p - cy * nblk;
-    int cx = 16 * blk + col;
+  // tiles (candidate row cy, 16-column block blk) in row-major order, every
+  // nwaves-th one; the walk is wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  int cy = 0, blk = wv;
+  while (blk >= nblk) blk -= nblk, cy++;
+  for (; cy < g.ny;) {
+    const int cx = 16 * blk + col;
     uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * 64 + cx);
     uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * 64 + cx);
     i32x4 B;
@@ -264,17 +276,27 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     B[3] = (int)(uint32_t)(r1 >> 32);
     i32x4 D = {0, 0, 0, 0};
     D = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, D, 0, 0, 0);
-    int nqc = nq[cy * 48 + cx];
+    const int nqc = nq[cy * 48 + cx];
+    const int t = cy * SW + cx;
+    const bool in_rows = (unsigned)(cy - mwy) < (unsigned)SH;
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      int wyy = cy - mwy[v], wxx = cx - mwx[v];
-      if (mval[v] && (unsigned)wyy < (unsigned)SH && (unsigned)wxx < (unsigned)SW) {
-        int dd = mnp[v] + nqc - 2 * D[v];
-        bool isref = cy == mry[v] && cx == mrx[v];
-        uint32_t key = (!isref && (uint32_t)dd <= thr) ? (((uint32_t)dd << 10) | (uint32_t)(wyy * SW + wxx))
-                                                       : kNone32;
-        keys[(4 * q + v) * SS + wyy * SW + wxx] = key;
-      }
+      const uint32_t dd = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
+      const uint32_t key = dd <= thr ? ((dd << 10) | (uint32_t)(t + wofs[v])) : kNone32;
+      if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW) keys[slot[v] + t] = key;
+    }
+    blk += nwaves;
+    while (blk >= nblk) blk -= nblk, cy++;
+  }
+  __syncthreads();
+  // a reference is not its own candidate
+  if (tid < 16) {
+    int a = tid >> 2, b = tid & 3;
+    if (a < g.nri && b < g.nci) {
+      int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
+      window_1d(ry, h, S, wy, t0);
+      window_1d(rx, w, S, wx, t0);
+      keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;
     }
   }
   __syncthreads();
