@@ -260,6 +260,51 @@ __device__ int select_group(const K (&k)[16], int nmax, K* buf, K& sel) {
   return n;
 }
 
+// Step-2 variant on FP32 distances.  db[t] = bit pattern of a non-negative
+// distance (~0u = not a candidate), wi[t] = its window index; the order is
+// (distance, window index) as 64-bit keys (bits << 32 | index).  The bound
+// theta is taken on 32-bit keys whose distance keeps only its top 22 bits
+// (monotone in the distance), and every candidate whose truncated distance
+// does not exceed theta's survives: a candidate above it has n-1 others with
+// strictly smaller distances, so it cannot be among the n-1 smallest.  Only
+// the survivors are sorted on full 64-bit keys.  Result as select_group.
+__device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t (&wi)[16], int nmax,
+                                       uint64_t* buf, uint64_t& sel) {
+  const uint32_t NONE = ~0u;
+  const int l = lane_id();
+  int npass = 0;
+#pragma unroll
+  for (int t = 0; t < 16; t++) npass += __popcll(__ballot(db[t] != NONE));
+  int m = 1 + npass < nmax ? 1 + npass : nmax;
+  int n = 1 << (31 - __clz(m));
+  sel = ~0ull;
+  if (n == 1) return 1;
+  const int want = n - 1;
+  uint32_t mn = NONE;
+#pragma unroll
+  for (int t = 0; t < 16; t++) mn = kmin(mn, db[t] == NONE ? NONE : ((db[t] & ~0x3FFu) | wi[t]));
+  const uint32_t th = lane_value<uint32_t>(wave_sort(mn), want - 1) >> 10;
+  int base = 0;
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int t = 0; t < 16; t++) {
+    bool p = db[t] != NONE && (db[t] >> 10) <= th;
+    uint64_t b = __ballot(p);
+    if (p) buf[base + __popcll(b & lt)] = ((uint64_t)db[t] << 32) | wi[t];
+    base += __popcll(b);
+  }
+  wave_lds_sync();
+  uint64_t res = ~0ull;
+  for (int c0 = 0; c0 < base; c0 += 64) {
+    uint64_t v = (c0 + l < base) ? buf[c0 + l] : ~0ull;
+    v = wave_sort(v);
+    res = (c0 == 0) ? v : wave_merge_low(res, v);
+  }
+  wave_lds_sync();
+  sel = res;
+  return n;
+}
+
 // ------------------------------------------------- MFMA 16x16 fragments ---
 // A 16x16 operand tile held as 4 values per lane: lane l, value v stands for
 // (row or column l%16, contraction index 4*(l/16)+v).  The accumulator tile

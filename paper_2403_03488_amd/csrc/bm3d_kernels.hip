@@ -402,16 +402,17 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
         }
       }
     }
-    uint64_t k[16];
+    uint32_t db[16], wi[16];
 #pragma unroll
     for (int c = 0; c < 16; c++) {
       int wxx = wxx0 + c;
       bool isref = (wyr + wyy == ryr) && (wxr + wxx == rxr);
       bool ok = lane_ok && wxx < SW && !isref && acc[c] <= thr;
-      k[c] = ok ? (((uint64_t)__float_as_uint(acc[c]) << 32) | (uint64_t)(wyy * SW + wxx)) : kNone64;
+      db[c] = ok ? __float_as_uint(acc[c]) : kNone32;
+      wi[c] = (uint32_t)(wyy * SW + wxx);
     }
     uint64_t sel;
-    int n = select_group<uint64_t>(k, nmax, bufs + (size_t)wave * SS, sel);
+    int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * SS, sel);
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx2 + r * nmax;
     if (l == 0) {
