@@ -150,9 +150,13 @@ __device__ inline BlockGeom block_geom(int h, int w, int nr, int nc, int S, int 
 
 // =========================================================== step-1 match ==
 // LDS: int8 luminance region [(S+16) rows][64 B], candidate norms
-// [(S+9)][48] int32, keys [16 refs][SH*SW] uint32 (also row-sum scratch).
+// [(S+9)][48] int32, keys of one pass [8 refs][SH*SW] uint32 (also row-sum
+// scratch).  The 16 references of a block are matched in two passes of 8
+// (reference columns 0-1, then 2-3), which halves the key buffer so that
+// three blocks fit a CU.
+constexpr int kM1Passes = 2, kM1PassRefs = 16 / kM1Passes;
 __host__ __device__ inline size_t match1_lds_bytes(int S) {
-  size_t keys = (size_t)16 * S * S * 4, rs = (size_t)(S + 16) * 48 * 4;
+  size_t keys = (size_t)kM1PassRefs * S * S * 4, rs = (size_t)(S + 16) * 48 * 4;
   return (size_t)(S + 16) * 64 + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
 }
 
@@ -246,7 +250,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     window_1d(ry, h, S, wy, t0);
     mwy = wy - g.uy0;
   }
-  int mwx[4], wofs[4], slot[4], mnp[4];
+  int mwx[4], wofs[4], mnp[4];
 #pragma unroll
   for (int v = 0; v < 4; v++) {
     const bool ok = row_ok && v < g.nci;
@@ -256,79 +260,89 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     // an absent reference gets an origin no candidate column can reach
     mwx[v] = ok ? wx - g.ux0 : -(1 << 20);
     wofs[v] = -(mwy * SW + (wx - g.ux0));
-    slot[v] = (4 * q + v) * SS + wofs[v];
     mnp[v] = nq[(ry - g.uy0) * 48 + (rx - g.ux0)];
   }
   const uint32_t thr = d.thr1;
-  // tiles (candidate row cy, 16-column block blk) in row-major order, every
-  // nwaves-th one; the walk is wave-uniform
   const int wv = __builtin_amdgcn_readfirstlane(wave);
-  int cy = 0, blk = wv;
-  while (blk >= nblk) blk -= nblk, cy++;
-  for (; cy < g.ny;) {
-    const int cx = 16 * blk + col;
-    uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * 64 + cx);
-    uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * 64 + cx);
-    i32x4 B;
-    B[0] = (int)(uint32_t)r0;
-    B[1] = (int)(uint32_t)(r0 >> 32);
-    B[2] = (int)(uint32_t)r1;
-    B[3] = (int)(uint32_t)(r1 >> 32);
-    i32x4 D = {0, 0, 0, 0};
-    D = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, D, 0, 0, 0);
-    const int nqc = nq[cy * 48 + cx];
-    const int t = cy * SW + cx;
-    const bool in_rows = (unsigned)(cy - mwy) < (unsigned)SH;
+
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const uint32_t dd = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
-      const uint32_t key = dd <= thr ? ((dd << 10) | (uint32_t)(t + wofs[v])) : kNone32;
-      if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW) keys[slot[v] + t] = key;
-    }
-    blk += nwaves;
+  for (int pass = 0; pass < kM1Passes; pass++) {
+    // this pass: reference columns v = 2*pass, 2*pass+1; local reference
+    // index 2q + (v - 2*pass), key slot lr*SS + widx
+    int slot[2];
+#pragma unroll
+    for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * SS + wofs[2 * pass + i];
+    // tiles (candidate row cy, 16-column block blk) in row-major order,
+    // every nwaves-th one; the walk is wave-uniform
+    int cy = 0, blk = wv;
     while (blk >= nblk) blk -= nblk, cy++;
-  }
-  __syncthreads();
-  // a reference is not its own candidate
-  if (tid < 16) {
-    int a = tid >> 2, b = tid & 3;
-    if (a < g.nri && b < g.nci) {
+    for (; cy < g.ny;) {
+      const int cx = 16 * blk + col;
+      uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * 64 + cx);
+      uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * 64 + cx);
+      i32x4 B;
+      B[0] = (int)(uint32_t)r0;
+      B[1] = (int)(uint32_t)(r0 >> 32);
+      B[2] = (int)(uint32_t)r1;
+      B[3] = (int)(uint32_t)(r1 >> 32);
+      i32x4 D = {0, 0, 0, 0};
+      D = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, D, 0, 0, 0);
+      const int nqc = nq[cy * 48 + cx];
+      const int t = cy * SW + cx;
+      const bool in_rows = (unsigned)(cy - mwy) < (unsigned)SH;
+#pragma unroll
+      for (int i = 0; i < 2; i++) {
+        const int v = 2 * pass + i;
+        const uint32_t dd = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
+        const uint32_t key = dd <= thr ? ((dd << 10) | (uint32_t)(t + wofs[v])) : kNone32;
+        if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW) keys[slot[i] + t] = key;
+      }
+      blk += nwaves;
+      while (blk >= nblk) blk -= nblk, cy++;
+    }
+    __syncthreads();
+    // a reference is not its own candidate
+    if (tid < kM1PassRefs) {
+      const int a = tid >> 1, b = 2 * pass + (tid & 1);
+      if (a < g.nri && b < g.nci) {
+        int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
+        window_1d(ry, h, S, wy, t0);
+        window_1d(rx, w, S, wx, t0);
+        keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;
+      }
+    }
+    __syncthreads();
+
+    for (int m = wave; m < kM1PassRefs; m += nwaves) {
+      const int a = m >> 1, b = 2 * pass + (m & 1);
+      if (a >= g.nri || b >= g.nci) continue;
+      uint32_t k[16];
+#pragma unroll
+      for (int t = 0; t < 16; t++) {
+        int i = l + 64 * t;
+        k[t] = i < SS ? keys[m * SS + i] : kNone32;
+      }
+      uint32_t sel;
+      int n = select_group<uint32_t>(k, nmax, keys + m * SS, sel);
       int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
       window_1d(ry, h, S, wy, t0);
       window_1d(rx, w, S, wx, t0);
-      keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;
-    }
-  }
-  __syncthreads();
-
-  for (int m = wave; m < 16; m += nwaves) {
-    int a = m >> 2, b = m & 3;
-    if (a >= g.nri || b >= g.nci) continue;
-    uint32_t k[16];
-#pragma unroll
-    for (int t = 0; t < 16; t++) {
-      int i = l + 64 * t;
-      k[t] = i < SS ? keys[m * SS + i] : kNone32;
-    }
-    uint32_t sel;
-    int n = select_group<uint32_t>(k, nmax, keys + m * SS, sel);
-    int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
-    window_1d(ry, h, S, wy, t0);
-    window_1d(rx, w, S, wx, t0);
-    size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
-    int32_t* o = d.idx1 + r * nmax;
-    if (l == 0) {
-      stg(o, ry * w + rx);
-      stg(d.cnt1 + r, n);
-    }
-    if (l + 1 < nmax) {
-      int gi = -1;
-      if (l < n - 1) {
-        int widx = (int)(sel & 1023u);
-        gi = (wy + widx / SW) * w + wx + widx % SW;
+      size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
+      int32_t* o = d.idx1 + r * nmax;
+      if (l == 0) {
+        stg(o, ry * w + rx);
+        stg(d.cnt1 + r, n);
       }
-      stg(o + l + 1, gi);
+      if (l + 1 < nmax) {
+        int gi = -1;
+        if (l < n - 1) {
+          int widx = (int)(sel & 1023u);
+          gi = (wy + widx / SW) * w + wx + widx % SW;
+        }
+        stg(o + l + 1, gi);
+      }
     }
+    __syncthreads();  // the next pass rewrites the key buffer
   }
 }
 
