@@ -293,9 +293,9 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
       for (int i = 0; i < 2; i++) {
         const int v = 2 * pass + i;
-        const uint32_t dd = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
-        const uint32_t key = dd <= thr ? ((dd << 10) | (uint32_t)(t + wofs[v])) : kNone32;
-        if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW) keys[slot[i] + t] = key;
+        // the distance alone; the key is formed when the slot is read back
+        if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
+          keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
       }
       blk += nwaves;
       while (blk >= nblk) blk -= nblk, cy++;
@@ -308,7 +308,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
         int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
         window_1d(ry, h, S, wy, t0);
         window_1d(rx, w, S, wx, t0);
-        keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;
+        keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;  // above any threshold
       }
     }
     __syncthreads();
@@ -316,11 +316,14 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     for (int m = wave; m < kM1PassRefs; m += nwaves) {
       const int a = m >> 1, b = 2 * pass + (m & 1);
       if (a >= g.nri || b >= g.nci) continue;
+      // key = distance << 10 | window index for candidates within the
+      // threshold (the distance is at most 2^22 - 1 there)
       uint32_t k[16];
 #pragma unroll
       for (int t = 0; t < 16; t++) {
-        int i = l + 64 * t;
-        k[t] = i < SS ? keys[m * SS + i] : kNone32;
+        const int i = l + 64 * t;
+        const uint32_t dd = i < SS ? keys[m * SS + i] : kNone32;
+        k[t] = dd <= thr ? ((dd << 10) | (uint32_t)i) : kNone32;
       }
       uint32_t sel;
       int n = select_group<uint32_t>(k, nmax, keys + m * SS, sel);
