@@ -149,15 +149,20 @@ __device__ inline BlockGeom block_geom(int h, int w, int nr, int nc, int S, int 
 }
 
 // =========================================================== step-1 match ==
-// LDS: int8 luminance region [(S+16) rows][64 B], candidate norms
-// [(S+9)][48] int32, keys of one pass [8 refs][SH*SW] uint32 (also row-sum
-// scratch).  The 16 references of a block are matched in two passes of 8
+// LDS: int8 luminance region [(S+16) rows][64 B used of kM1Pitch],
+// candidate norms [(S+9)][48] int32, keys of one pass [8 refs][S*S+8]
+// uint32 (also row-sum scratch).  The 16 references of a block are matched in two passes of 8
 // (reference columns 0-1, then 2-3), which halves the key buffer so that
 // three blocks fit a CU.
-constexpr int kM1Passes = 2, kM1PassRefs = 16 / kM1Passes;
+// Row pitches are padded against LDS bank conflicts: region rows 80 B apart
+// (the four lane groups of a fragment read rows 2 apart, 40 dwords = 8 banks
+// mod 32), and per-reference key slots S*S+8 apart (lane groups store to
+// references 2 apart, 16 banks mod 32).
+constexpr int kM1Passes = 2, kM1PassRefs = 16 / kM1Passes, kM1Pitch = 80;
+__host__ __device__ inline int match1_key_stride(int S) { return S * S + 8; }
 __host__ __device__ inline size_t match1_lds_bytes(int S) {
-  size_t keys = (size_t)kM1PassRefs * S * S * 4, rs = (size_t)(S + 16) * 48 * 4;
-  return (size_t)(S + 16) * 64 + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
+  size_t keys = (size_t)kM1PassRefs * match1_key_stride(S) * 4, rs = (size_t)(S + 16) * 48 * 4;
+  return (size_t)(S + 16) * kM1Pitch + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
 }
 
 // 8 bytes starting at byte offset off of an LDS buffer (dword-aligned base).
@@ -184,7 +189,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
   const int NX = 16 * nblk;
 
   uint8_t* reg = (uint8_t*)smem;
-  int32_t* nq = (int32_t*)(smem + (size_t)(S + 16) * 64);
+  int32_t* nq = (int32_t*)(smem + (size_t)(S + 16) * kM1Pitch);
+  const int RS = match1_key_stride(S);
   uint32_t* keys = (uint32_t*)(nq + (size_t)(S + 9) * 48);
   int32_t* rs = (int32_t*)keys;
 
@@ -203,7 +209,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
     for (int k = 0; k < kMaxIt; k++) {
       int i = tid + k * 256;
-      if (i < RR * 64) reg[i] = (g.ux0 + (i & 63) < w) ? (uint8_t)(v[k] ^ 0x80u) : (uint8_t)0;
+      if (i < RR * 64)
+        reg[(i >> 6) * kM1Pitch + (i & 63)] = (g.ux0 + (i & 63) < w) ? (uint8_t)(v[k] ^ 0x80u) : (uint8_t)0;
     }
   }
   __syncthreads();
@@ -211,7 +218,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
   for (int i = tid; i < RR * NX; i += blockDim.x) {
     int y = i / NX, x = i - y * NX, s = 0;
     for (int v = 0; v < kP; v++) {
-      int e = (int8_t)reg[y * 64 + x + v];
+      int e = (int8_t)reg[y * kM1Pitch + x + v];
       s += e * e;
     }
     rs[y * 48 + x] = s;
@@ -230,8 +237,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     int a = col >> 2, b = col & 3;
     if (a < g.nri && b < g.nci) {
       int ry = ref_pos(g.ri0 + a, h) - g.uy0, rx = ref_pos(g.ci0 + b, w) - g.ux0;
-      uint64_t r0 = lds_bytes8(reg, (ry + 2 * q) * 64 + rx);
-      uint64_t r1 = lds_bytes8(reg, (ry + 2 * q + 1) * 64 + rx);
+      uint64_t r0 = lds_bytes8(reg, (ry + 2 * q) * kM1Pitch + rx);
+      uint64_t r1 = lds_bytes8(reg, (ry + 2 * q + 1) * kM1Pitch + rx);
       A[0] = (int)(uint32_t)r0;
       A[1] = (int)(uint32_t)(r0 >> 32);
       A[2] = (int)(uint32_t)r1;
@@ -241,8 +248,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
   // accumulator rows 4q+v are references (row q, column v) of the block.
   // The window origin row depends on the reference row only (q), the origin
   // column on the reference column (v).  A candidate at union position
-  // (cy, cx) has window index widx = cy*SW + cx - (wy*SW + wx) and key slot
-  // (4q+v)*SS + widx.
+  // (cy, cx) has window index widx = cy*SW + cx - (wy*SW + wx).
   const bool row_ok = q < g.nri;
   int mwy;
   {
@@ -268,18 +274,18 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
   for (int pass = 0; pass < kM1Passes; pass++) {
     // this pass: reference columns v = 2*pass, 2*pass+1; local reference
-    // index 2q + (v - 2*pass), key slot lr*SS + widx
+    // index lr = 2q + (v - 2*pass), key slot lr*RS + widx
     int slot[2];
 #pragma unroll
-    for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * SS + wofs[2 * pass + i];
+    for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * RS + wofs[2 * pass + i];
     // tiles (candidate row cy, 16-column block blk) in row-major order,
     // every nwaves-th one; the walk is wave-uniform
     int cy = 0, blk = wv;
     while (blk >= nblk) blk -= nblk, cy++;
     for (; cy < g.ny;) {
       const int cx = 16 * blk + col;
-      uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * 64 + cx);
-      uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * 64 + cx);
+      uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * kM1Pitch + cx);
+      uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * kM1Pitch + cx);
       i32x4 B;
       B[0] = (int)(uint32_t)r0;
       B[1] = (int)(uint32_t)(r0 >> 32);
@@ -308,7 +314,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
         int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
         window_1d(ry, h, S, wy, t0);
         window_1d(rx, w, S, wx, t0);
-        keys[tid * SS + (ry - wy) * SW + (rx - wx)] = kNone32;  // above any threshold
+        keys[tid * RS + (ry - wy) * SW + (rx - wx)] = kNone32;  // above any threshold
       }
     }
     __syncthreads();
@@ -322,11 +328,11 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
       for (int t = 0; t < 16; t++) {
         const int i = l + 64 * t;
-        const uint32_t dd = i < SS ? keys[m * SS + i] : kNone32;
+        const uint32_t dd = i < SS ? keys[m * RS + i] : kNone32;
         k[t] = dd <= thr ? ((dd << 10) | (uint32_t)i) : kNone32;
       }
       uint32_t sel;
-      int n = select_group<uint32_t>(k, nmax, keys + m * SS, sel);
+      int n = select_group<uint32_t>(k, nmax, keys + m * RS, sel);
       int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
       window_1d(ry, h, S, wy, t0);
       window_1d(rx, w, S, wx, t0);
