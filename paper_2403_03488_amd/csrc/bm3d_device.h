@@ -155,33 +155,43 @@ constexpr uint64_t bitonic_min_lanes(int KB, int J) {
     if (((l & J) == 0) == ((l & KB) == 0)) m |= 1ull << l;
   return m;
 }
-// one compare-exchange step at lane distance J; lanes in MINL keep the minimum
-template <class K, int J, uint64_t MINL> __device__ inline K cmp_xchg(K v) {
-  const K o = xor_lane_k<K, J>(v);
-  const bool keep = (v < o) == lane_in(MINL);
-  return keep ? v : o;
+// One compare-exchange step at lane distance J on NR independent values
+// (interleaved for instruction-level parallelism); lanes in MINL keep the
+// minimum.
+template <class K, int J, uint64_t MINL, int NR> __device__ inline void cmp_xchg(K (&v)[NR]) {
+  K o[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) o[r] = xor_lane_k<K, J>(v[r]);
+  const bool m = lane_in(MINL);
+#pragma unroll
+  for (int r = 0; r < NR; r++) v[r] = ((v[r] < o[r]) == m) ? v[r] : o[r];
 }
-template <class K, int KB, int J> __device__ inline K bitonic_steps(K v) {
-  v = cmp_xchg<K, J, bitonic_min_lanes(KB, J)>(v);
-  if constexpr (J > 1) v = bitonic_steps<K, KB, J / 2>(v);
-  return v;
+template <class K, int KB, int J, int NR> __device__ inline void bitonic_steps(K (&v)[NR]) {
+  cmp_xchg<K, J, bitonic_min_lanes(KB, J), NR>(v);
+  if constexpr (J > 1) bitonic_steps<K, KB, J / 2, NR>(v);
 }
-template <class K, int KB> __device__ inline K bitonic_stages(K v) {
-  v = bitonic_steps<K, KB, KB / 2>(v);
-  if constexpr (KB < 64) v = bitonic_stages<K, KB * 2>(v);
-  return v;
+template <class K, int KB, int NR> __device__ inline void bitonic_stages(K (&v)[NR]) {
+  bitonic_steps<K, KB, KB / 2, NR>(v);
+  if constexpr (KB < 64) bitonic_stages<K, KB * 2, NR>(v);
 }
-// Bitonic sort of one key per lane across the wave, ascending by lane.
-template <class K> __device__ inline K wave_sort(K v) { return bitonic_stages<K, 2>(v); }
+// Bitonic sort of one key per lane across the wave, ascending by lane (NR
+// independent sorts side by side).
+template <class K, int NR> __device__ inline void wave_sort_n(K (&v)[NR]) { bitonic_stages<K, 2, NR>(v); }
+template <class K> __device__ inline K wave_sort(K v) {
+  K a[1] = {v};
+  wave_sort_n<K, 1>(a);
+  return a[0];
+}
 
-// a, b ascending across lanes -> the 64 smallest of a U b, ascending.
-template <class K, int J> __device__ inline K half_clean(K m) {
-  m = cmp_xchg<K, J, bitonic_min_lanes(64, J)>(m);
-  if constexpr (J > 1) m = half_clean<K, J / 2>(m);
-  return m;
+// a, b ascending across lanes -> a = the 64 smallest of a U b, ascending.
+template <class K, int J, int NR> __device__ inline void half_clean(K (&m)[NR]) {
+  cmp_xchg<K, J, bitonic_min_lanes(64, J), NR>(m);
+  if constexpr (J > 1) half_clean<K, J / 2, NR>(m);
 }
-template <class K> __device__ inline K wave_merge_low(K a, K b) {
-  return half_clean<K, 32>(kmin(a, reverse_lanes<K>(b)));
+template <class K, int NR> __device__ inline void wave_merge_low_n(K (&a)[NR], const K (&b)[NR]) {
+#pragma unroll
+  for (int r = 0; r < NR; r++) a[r] = kmin(a[r], reverse_lanes<K>(b[r]));
+  half_clean<K, 32, NR>(a);
 }
 
 __device__ inline int wave_sum_i(int v) {
@@ -214,50 +224,72 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Group selection shared by both matching steps.  Each lane holds 16 keys
-// (kmax<K> = not a candidate); keys order candidates by (distance, window
-// index).  Returns the group size n = largest power of two <=
-// min(1 + #candidates, nmax); lanes 0..n-2 receive the n-1 smallest keys in
-// ascending order in `sel`.  `buf` is wave-private LDS scratch of at least
+// Group selection shared by both matching steps, for NR references at once
+// (their dependency chains interleave).  Each lane holds 16 keys per
+// reference (all ones = not a candidate); keys order candidates by
+// (distance, window index).  n[r] = largest power of two <= min(1 +
+// #candidates, nmax); lanes 0..n-2 receive the n-1 smallest keys in
+// ascending order in sel[r].  buf[r] is wave-private LDS scratch of at least
 // as many entries as there are candidates (may alias the keys' source).
-template <class K>
-__device__ int select_group(const K (&k)[16], int nmax, K* buf, K& sel) {
+template <class K, int NR>
+__device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR], K (&sel)[NR],
+                             int (&n)[NR]) {
   const K NONE = ~(K)0;
   const int l = lane_id();
-  int npass = 0;
+  K mn[NR];
 #pragma unroll
-  for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[t] != NONE));
-  int m = 1 + npass < nmax ? 1 + npass : nmax;
-  int n = 1 << (31 - __clz(m));
-  sel = NONE;
-  if (n == 1) return 1;
-  const int want = n - 1;
-  // Upper bound on the want-th smallest key: the want-th smallest of the
-  // per-lane minima (those are `want` distinct candidates at or below it).
-  K mn = k[0];
+  for (int r = 0; r < NR; r++) {
+    int npass = 0;
 #pragma unroll
-  for (int t = 1; t < 16; t++) mn = kmin(mn, k[t]);
-  K theta = lane_value<K>(wave_sort(mn), want - 1);
-  // compact the survivors (candidates with key <= theta) into buf
-  int base = 0;
+    for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[r][t] != NONE));
+    const int m = 1 + npass < nmax ? 1 + npass : nmax;
+    n[r] = 1 << (31 - __clz(m));
+    mn[r] = k[r][0];
+#pragma unroll
+    for (int t = 1; t < 16; t++) mn[r] = kmin(mn[r], k[r][t]);
+  }
+  // Upper bound on the (n-1)-th smallest key: the (n-1)-th smallest of the
+  // per-lane minima (those are n-1 distinct candidates at or below it).
+  wave_sort_n<K, NR>(mn);
+  K theta[NR];
+  int base[NR];
   const uint64_t lt = lanemask_lt();
 #pragma unroll
+  for (int r = 0; r < NR; r++) {
+    theta[r] = n[r] > 1 ? lane_value<K>(mn[r], n[r] - 2) : (K)0;
+    base[r] = 0;
+  }
+  // compact the survivors (candidates with key <= theta) into buf
+#pragma unroll
   for (int t = 0; t < 16; t++) {
-    bool p = k[t] <= theta && k[t] != NONE;
-    uint64_t b = __ballot(p);
-    if (p) buf[base + __popcll(b & lt)] = k[t];
-    base += __popcll(b);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      const bool p = n[r] > 1 && k[r][t] <= theta[r] && k[r][t] != NONE;
+      const uint64_t b = __ballot(p);
+      if (p) buf[r][base[r] + __popcll(b & lt)] = k[r][t];
+      base[r] += __popcll(b);
+    }
   }
   wave_lds_sync();
-  K res = NONE;
-  for (int c0 = 0; c0 < base; c0 += 64) {
-    K v = (c0 + l < base) ? buf[c0 + l] : NONE;
-    v = wave_sort(v);
-    res = (c0 == 0) ? v : wave_merge_low(res, v);
+  int cmax = 0;
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    sel[r] = NONE;
+    cmax = base[r] > cmax ? base[r] : cmax;
+  }
+  for (int c0 = 0; c0 < cmax; c0 += 64) {
+    K v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) v[r] = (c0 + l < base[r]) ? buf[r][c0 + l] : NONE;
+    wave_sort_n<K, NR>(v);
+    if (c0 == 0) {
+#pragma unroll
+      for (int r = 0; r < NR; r++) sel[r] = v[r];
+    } else {
+      wave_merge_low_n<K, NR>(sel, v);
+    }
   }
   wave_lds_sync();
-  sel = res;
-  return n;
 }
 
 // Step-2 variant on FP32 distances.  db[t] = bit pattern of a non-negative
@@ -294,14 +326,17 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t 
     base += __popcll(b);
   }
   wave_lds_sync();
-  uint64_t res = ~0ull;
+  uint64_t res[1] = {~0ull};
   for (int c0 = 0; c0 < base; c0 += 64) {
-    uint64_t v = (c0 + l < base) ? buf[c0 + l] : ~0ull;
-    v = wave_sort(v);
-    res = (c0 == 0) ? v : wave_merge_low(res, v);
+    uint64_t v[1] = {(c0 + l < base) ? buf[c0 + l] : ~0ull};
+    wave_sort_n<uint64_t, 1>(v);
+    if (c0 == 0)
+      res[0] = v[0];
+    else
+      wave_merge_low_n<uint64_t, 1>(res, v);
   }
   wave_lds_sync();
-  sel = res;
+  sel = res[0];
   return n;
 }
 

@@ -214,20 +214,31 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     }
   }
   __syncthreads();
-  // |q|^2 of every union candidate: 8-wide row sums, then 8-tall column sums
+  // |q|^2 of every union candidate: 8-wide row sums (two 4-way int8 dot
+  // products), then 8-tall column sums, each thread sliding down one run of
+  // rows of one column
   for (int i = tid; i < RR * NX; i += blockDim.x) {
-    int y = i / NX, x = i - y * NX, s = 0;
-    for (int v = 0; v < kP; v++) {
-      int e = (int8_t)reg[y * kM1Pitch + x + v];
-      s += e * e;
-    }
-    rs[y * 48 + x] = s;
+    const int y = i / NX, x = i - y * NX;
+    const uint64_t e8 = lds_bytes8(reg, y * kM1Pitch + x);
+    const int lo = (int)(uint32_t)e8, hi = (int)(uint32_t)(e8 >> 32);
+    rs[y * 48 + x] = __builtin_amdgcn_sdot4(lo, lo, __builtin_amdgcn_sdot4(hi, hi, 0, false), false);
   }
   __syncthreads();
-  for (int i = tid; i < g.ny * NX; i += blockDim.x) {
-    int y = i / NX, x = i - y * NX, s = 0;
-    for (int u = 0; u < kP; u++) s += rs[(y + u) * 48 + x];
-    nq[y * 48 + x] = s;
+  {
+    const int runs = max(1, (int)blockDim.x / NX);
+    const int len = (g.ny + runs - 1) / runs;
+    const int x = tid % NX, y0 = (tid / NX) * len;
+    const int y1 = min(g.ny, y0 + len);
+    if (tid < runs * NX && y0 < y1) {
+      int sacc = 0;
+#pragma unroll
+      for (int u = 0; u < kP; u++) sacc += rs[(y0 + u) * 48 + x];
+      nq[y0 * 48 + x] = sacc;
+      for (int y = y0 + 1; y < y1; y++) {
+        sacc += rs[(y + kP - 1) * 48 + x] - rs[(y - 1) * 48 + x];
+        nq[y * 48 + x] = sacc;
+      }
+    }
   }
   __syncthreads();
 
@@ -279,31 +290,49 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
     for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * RS + wofs[2 * pass + i];
     // tiles (candidate row cy, 16-column block blk) in row-major order,
-    // every nwaves-th one; the walk is wave-uniform
+    // every nwaves-th one, two per iteration; the walk is wave-uniform
     int cy = 0, blk = wv;
     while (blk >= nblk) blk -= nblk, cy++;
-    for (; cy < g.ny;) {
-      const int cx = 16 * blk + col;
-      uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * kM1Pitch + cx);
-      uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * kM1Pitch + cx);
-      i32x4 B;
-      B[0] = (int)(uint32_t)r0;
-      B[1] = (int)(uint32_t)(r0 >> 32);
-      B[2] = (int)(uint32_t)r1;
-      B[3] = (int)(uint32_t)(r1 >> 32);
-      i32x4 D = {0, 0, 0, 0};
-      D = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, D, 0, 0, 0);
-      const int nqc = nq[cy * 48 + cx];
-      const int t = cy * SW + cx;
-      const bool in_rows = (unsigned)(cy - mwy) < (unsigned)SH;
+    while (cy < g.ny) {
+      int cy2 = cy, blk2 = blk + nwaves;
+      while (blk2 >= nblk) blk2 -= nblk, cy2++;
+      const bool two = cy2 < g.ny;
+      const int cyb = two ? cy2 : cy, blkb = two ? blk2 : blk;  // in-range stand-in
+      i32x4 Bm[2];
 #pragma unroll
-      for (int i = 0; i < 2; i++) {
-        const int v = 2 * pass + i;
-        // the distance alone; the key is formed when the slot is read back
-        if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
-          keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc - 2 * D[v]);
+      for (int j = 0; j < 2; j++) {
+        const int yy = j ? cyb : cy, xx = 16 * (j ? blkb : blk) + col;
+        const uint64_t r0 = lds_bytes8(reg, (yy + 2 * q) * kM1Pitch + xx);
+        const uint64_t r1 = lds_bytes8(reg, (yy + 2 * q + 1) * kM1Pitch + xx);
+        Bm[j][0] = (int)(uint32_t)r0;
+        Bm[j][1] = (int)(uint32_t)(r0 >> 32);
+        Bm[j][2] = (int)(uint32_t)r1;
+        Bm[j][3] = (int)(uint32_t)(r1 >> 32);
       }
-      blk += nwaves;
+      const int nqc0 = nq[cy * 48 + 16 * blk + col], nqc1 = nq[cyb * 48 + 16 * blkb + col];
+      i32x4 Dm[2];
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        const i32x4 z = {0, 0, 0, 0};
+        Dm[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, Bm[j], z, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        if (j == 1 && !two) break;
+        const int yy = j ? cyb : cy, cx = 16 * (j ? blkb : blk) + col;
+        const int nqc = j ? nqc1 : nqc0;
+        const int t = yy * SW + cx;
+        const bool in_rows = (unsigned)(yy - mwy) < (unsigned)SH;
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+          const int v = 2 * pass + i;
+          // the distance alone; the key is formed when the slot is read back
+          if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
+            keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc - 2 * Dm[j][v]);
+        }
+      }
+      cy = cy2;
+      blk = blk2 + nwaves;
       while (blk >= nblk) blk -= nblk, cy++;
     }
     __syncthreads();
@@ -319,36 +348,52 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     }
     __syncthreads();
 
-    for (int m = wave; m < kM1PassRefs; m += nwaves) {
-      const int a = m >> 1, b = 2 * pass + (m & 1);
-      if (a >= g.nri || b >= g.nci) continue;
-      // key = distance << 10 | window index for candidates within the
-      // threshold (the distance is at most 2^22 - 1 there)
-      uint32_t k[16];
+    // each wave selects the groups of local references wave and wave + 4
+    static_assert(kM1PassRefs == 8, "two references per wave with four waves");
+    {
+      uint32_t k[2][16];
+      bool act[2];
+      uint32_t* buf[2];
 #pragma unroll
-      for (int t = 0; t < 16; t++) {
-        const int i = l + 64 * t;
-        const uint32_t dd = i < SS ? keys[m * RS + i] : kNone32;
-        k[t] = dd <= thr ? ((dd << 10) | (uint32_t)i) : kNone32;
-      }
-      uint32_t sel;
-      int n = select_group<uint32_t>(k, nmax, keys + m * RS, sel);
-      int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
-      window_1d(ry, h, S, wy, t0);
-      window_1d(rx, w, S, wx, t0);
-      size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
-      int32_t* o = d.idx1 + r * nmax;
-      if (l == 0) {
-        stg(o, ry * w + rx);
-        stg(d.cnt1 + r, n);
-      }
-      if (l + 1 < nmax) {
-        int gi = -1;
-        if (l < n - 1) {
-          int widx = (int)(sel & 1023u);
-          gi = (wy + widx / SW) * w + wx + widx % SW;
+      for (int r = 0; r < 2; r++) {
+        const int m = wave + 4 * r;
+        const int a = m >> 1, b = 2 * pass + (m & 1);
+        act[r] = m < kM1PassRefs && a < g.nri && b < g.nci;
+        buf[r] = keys + (act[r] ? m : 0) * RS;
+        // key = distance << 10 | window index for candidates within the
+        // threshold (the distance is at most 2^22 - 1 there)
+#pragma unroll
+        for (int t = 0; t < 16; t++) {
+          const int i = l + 64 * t;
+          const uint32_t dd = (act[r] && i < SS) ? keys[m * RS + i] : kNone32;
+          k[r][t] = dd <= thr ? ((dd << 10) | (uint32_t)i) : kNone32;
         }
-        stg(o + l + 1, gi);
+      }
+      uint32_t sel[2];
+      int n[2];
+      select_group<uint32_t, 2>(k, nmax, buf, sel, n);
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+        if (!act[r]) continue;
+        const int m = wave + 4 * r;
+        const int a = m >> 1, b = 2 * pass + (m & 1);
+        int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
+        window_1d(ry, h, S, wy, t0);
+        window_1d(rx, w, S, wx, t0);
+        size_t rr = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
+        int32_t* o = d.idx1 + rr * nmax;
+        if (l == 0) {
+          stg(o, ry * w + rx);
+          stg(d.cnt1 + rr, n[r]);
+        }
+        if (l + 1 < nmax) {
+          int gi = -1;
+          if (l < n[r] - 1) {
+            int widx = (int)(sel[r] & 1023u);
+            gi = (wy + widx / SW) * w + wx + widx % SW;
+          }
+          stg(o + l + 1, gi);
+        }
       }
     }
     __syncthreads();  // the next pass rewrites the key buffer
