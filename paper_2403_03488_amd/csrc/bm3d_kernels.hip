@@ -289,51 +289,43 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     int slot[2];
 #pragma unroll
     for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * RS + wofs[2 * pass + i];
-    // tiles (candidate row cy, 16-column block blk) in row-major order,
-    // every nwaves-th one, two per iteration; the walk is wave-uniform
-    int cy = 0, blk = wv;
-    while (blk >= nblk) blk -= nblk, cy++;
-    while (cy < g.ny) {
-      int cy2 = cy, blk2 = blk + nwaves;
-      while (blk2 >= nblk) blk2 -= nblk, cy2++;
-      const bool two = cy2 < g.ny;
-      const int cyb = two ? cy2 : cy, blkb = two ? blk2 : blk;  // in-range stand-in
-      i32x4 Bm[2];
+    // each wave takes whole candidate rows cy (every nwaves-th), all 16-column
+    // blocks of a row at once (at most 3: the union window is <= 48 wide)
+    for (int cy = wv; cy < g.ny; cy += nwaves) {
+      constexpr int kMaxBlk = (kMaxS + 16) / 16;
+      i32x4 Bm[kMaxBlk];
+      int nqc[kMaxBlk];
 #pragma unroll
-      for (int j = 0; j < 2; j++) {
-        const int yy = j ? cyb : cy, xx = 16 * (j ? blkb : blk) + col;
-        const uint64_t r0 = lds_bytes8(reg, (yy + 2 * q) * kM1Pitch + xx);
-        const uint64_t r1 = lds_bytes8(reg, (yy + 2 * q + 1) * kM1Pitch + xx);
+      for (int j = 0; j < kMaxBlk; j++) {
+        const int xx = 16 * (j < nblk ? j : 0) + col;  // in-range stand-in past the last block
+        const uint64_t r0 = lds_bytes8(reg, (cy + 2 * q) * kM1Pitch + xx);
+        const uint64_t r1 = lds_bytes8(reg, (cy + 2 * q + 1) * kM1Pitch + xx);
         Bm[j][0] = (int)(uint32_t)r0;
         Bm[j][1] = (int)(uint32_t)(r0 >> 32);
         Bm[j][2] = (int)(uint32_t)r1;
         Bm[j][3] = (int)(uint32_t)(r1 >> 32);
+        nqc[j] = nq[cy * 48 + xx];
       }
-      const int nqc0 = nq[cy * 48 + 16 * blk + col], nqc1 = nq[cyb * 48 + 16 * blkb + col];
-      i32x4 Dm[2];
+      i32x4 Dm[kMaxBlk];
 #pragma unroll
-      for (int j = 0; j < 2; j++) {
+      for (int j = 0; j < kMaxBlk; j++) {
         const i32x4 z = {0, 0, 0, 0};
         Dm[j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, Bm[j], z, 0, 0, 0);
       }
+      const bool in_rows = (unsigned)(cy - mwy) < (unsigned)SH;
 #pragma unroll
-      for (int j = 0; j < 2; j++) {
-        if (j == 1 && !two) break;
-        const int yy = j ? cyb : cy, cx = 16 * (j ? blkb : blk) + col;
-        const int nqc = j ? nqc1 : nqc0;
-        const int t = yy * SW + cx;
-        const bool in_rows = (unsigned)(yy - mwy) < (unsigned)SH;
+      for (int j = 0; j < kMaxBlk; j++) {
+        if (j >= nblk) break;
+        const int cx = 16 * j + col;
+        const int t = cy * SW + cx;
 #pragma unroll
         for (int i = 0; i < 2; i++) {
           const int v = 2 * pass + i;
           // the distance alone; the key is formed when the slot is read back
           if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
-            keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc - 2 * Dm[j][v]);
+            keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc[j] - 2 * Dm[j][v]);
         }
       }
-      cy = cy2;
-      blk = blk2 + nwaves;
-      while (blk >= nblk) blk -= nblk, cy++;
     }
     __syncthreads();
     // a reference is not its own candidate
