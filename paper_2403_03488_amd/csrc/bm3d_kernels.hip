@@ -559,7 +559,8 @@ __device__ inline typename XF::frag had_frag(int rt, int kt, int n) {
 
 // Builds the two DCT fragment tables of a workgroup (caller synchronises).
 template <class XF>
-__device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, float* Cm) {
+__device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, float* Cm,
+                              const float* kaiser) {
   const int tid = threadIdx.x;
   if (tid < 64) {
     int a = tid >> 3, u = tid & 7;
@@ -581,6 +582,8 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
         coef = 16 * (f & 3) + 4 * lq + v;
       }
       v4[v] = Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
+      // the inverse table carries the Kaiser weight of its output pixel
+      if (tab == 1) v4[v] *= kaiser[pix >> 3] * kaiser[pix & 7];
     }
     // stored so that the two tiles of one 32-deep contraction step are
     // adjacent for each lane: B at ((kt/2)*4 + nt, lane, kt%2), A at
@@ -824,9 +827,12 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           const frag* ta = tabA + ((mt * 2 + c2) * 64 + l) * 2;
           acc = XF::mma2(ta[0], ta[1], b3[2 * c2], b3[2 * c2 + 1], acc);
         }
+        // acc already holds K(pixel) times the filtered value; the centre
+        // (times the member weight) gets the same Kaiser weight here
+        const float kc = Ku[mt] * cw[gt];
         f32x4 add;
 #pragma unroll
-        for (int v = 0; v < 4; v++) add[v] = (Ku[mt] * Kv[v]) * (acc[v] + cw[gt]);
+        for (int v = 0; v < 4; v++) add[v] = __builtin_fmaf(kc, Kv[v], acc[v]);
         *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
       }
       if (q == 0 && mv[gt]) {
@@ -912,7 +918,7 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
   float* Cm = (float*)(tabA + 16 * 64);
-  filter_tables<XF>(tabB, tabA, Cm);
+  filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int wave = threadIdx.x >> 6;
@@ -940,7 +946,7 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
   float* Cm = (float*)(tabA + 16 * 64);
-  filter_tables<XF>(tabB, tabA, Cm);
+  filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int wave = threadIdx.x >> 6;
