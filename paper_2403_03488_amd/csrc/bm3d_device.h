@@ -74,6 +74,18 @@ struct KParams {
 #define BM3D_GLOBAL __attribute__((address_space(1)))
 template <class T> __device__ inline T ldg(const T* p) { return *(const BM3D_GLOBAL T*)p; }
 template <class T> __device__ inline void stg(T* p, T v) { *(BM3D_GLOBAL T*)p = v; }
+// Read-only data (descriptor tables) through the constant address space, so
+// that wave-uniform reads become scalar loads into SGPRs.
+#define BM3D_CONST __attribute__((address_space(4)))
+template <class T> __device__ inline T ldc(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "whole words");
+  T r;
+  const BM3D_CONST uint32_t* src = (const BM3D_CONST uint32_t*)p;
+  uint32_t* dst = (uint32_t*)&r;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); i++) dst[i] = src[i];
+  return r;
+}
 __device__ inline void gadd(float* p, float v) {
   __hip_atomic_fetch_add((BM3D_GLOBAL float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

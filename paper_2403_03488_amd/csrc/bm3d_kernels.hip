@@ -647,11 +647,23 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   frag Hf[2][2];  // Hadamard blocks of the current group size
   int hn = 0;
   const int nrefs = g.nri * g.nci;
+  // the group size and member slots of a reference are loaded one reference
+  // ahead (slots beyond the group hold -1 and are ignored below)
+  auto ref_of = [&](int j) { return (size_t)(g.ri0 + j / g.nci) * d.nc + g.ci0 + j % g.nci; };
+  int cnt_nx = 0, gi_nx[2] = {-1, -1};
+  auto prefetch = [&](int j) {
+    const size_t rn = ref_of(j);
+    cnt_nx = ldg(cnt + rn);
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) gi_nx[gt] = ldg(idx + rn * nmax + (16 * gt + col < nmax ? 16 * gt + col : 0));
+  };
+  if (nrefs > 0) prefetch(0);
   for (int j = 0; j < nrefs; j++) {
-    const int ri = g.ri0 + j / g.nci, ci = g.ci0 + j % g.nci;
-    const size_t r = (size_t)ri * d.nc + ci;
+    const size_t r = ref_of(j);
+    const int cnt_j = cnt_nx, gi_j[2] = {gi_nx[0], gi_nx[1]};
+    if (j + 1 < nrefs) prefetch(j + 1);
     // group size and everything derived from it are wave-uniform
-    const int n = __builtin_amdgcn_readfirstlane(min(max(ldg(cnt + r), 1), nmax));
+    const int n = __builtin_amdgcn_readfirstlane(min(max(cnt_j, 1), nmax));
     const int NG = n > 16 ? 2 : 1;
     const float rsn = n == 1 ? 1.f : n == 2 ? 0.70710678118654752f : n == 4 ? 0.5f
                     : n == 8 ? 0.35355339059327376f : n == 16 ? 0.25f : 0.17677669529663688f;
@@ -661,7 +673,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     for (int gt = 0; gt < 2; gt++) {
       int gm = 16 * gt + col;
       mv[gt] = gt < NG && gm < n;
-      int gi = ldg(idx + r * nmax + (mv[gt] ? gm : 0));
+      int gi = gi_j[gt];
       // gi / w through a float reciprocal, corrected by one either way
       int yy = (int)((float)gi * inv_w), xx = gi - yy * w;
       yy = xx < 0 ? yy - 1 : xx >= w ? yy + 1 : yy;
@@ -881,29 +893,42 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   for (int i = 0; i < 8; i++) kw[i] = kp.kaiser[i];
   for (int x0 = 0; x0 < RW; x0 += 64) {
     const int x = x0 + l;
+    const int xc = min(x, RW - 1);  // in-range address for lanes past the region
     float hsum[8];
 #pragma unroll
     for (int i = 0; i < 8; i++) hsum[i] = 0.f;
-    for (int y = 0; y < RH; y++) {
+    // four rows per iteration: all their LDS reads first, then the sums
+    for (int y0 = 0; y0 < RH; y0 += 4) {
+      float wv[4][8], nv[4];
 #pragma unroll
-      for (int i = 7; i > 0; i--) hsum[i] = hsum[i - 1];
-      float hsv = 0.f;
-      if (y < g.ny && x < RW) {
-        const float* wr = wW + y * WW;
+      for (int k = 0; k < 4; k++) {
+        const int y = y0 + k;
+        const float* wr = wW + min(y, g.ny - 1) * WW;
 #pragma unroll
         for (int v = 0; v < 8; v++) {
-          int px = x - v;
-          hsv += (px >= 0 && px < g.nx) ? kw[v] * wr[px] : 0.f;
+          const int px = x - v;
+          const float t = wr[min(max(px, 0), g.nx - 1)];
+          wv[k][v] = (y < g.ny && px >= 0 && px < g.nx) ? t : 0.f;
         }
+        nv[k] = wnum[min(y, RH - 1) * RP + xc];
       }
-      hsum[0] = hsv;
-      float dv = 0.f;
 #pragma unroll
-      for (int u = 0; u < 8; u++) dv += kw[u] * hsum[u];
-      if (x < RW && dv != 0.f) {
-        size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
-        gadd(gnum + o, wnum[y * RP + x]);
-        gadd(gden + o, dv);
+      for (int k = 0; k < 4; k++) {
+        const int y = y0 + k;
+#pragma unroll
+        for (int i = 7; i > 0; i--) hsum[i] = hsum[i - 1];
+        float hsv = 0.f;
+#pragma unroll
+        for (int v = 0; v < 8; v++) hsv += kw[v] * wv[k][v];
+        hsum[0] = hsv;
+        float dv = 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; u++) dv += kw[u] * hsum[u];
+        if (y < RH && x < RW && dv != 0.f) {
+          size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
+          gadd(gnum + o, nv[k]);
+          gadd(gden + o, dv);
+        }
       }
     }
   }
@@ -949,12 +974,15 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
-  const int wave = threadIdx.x >> 6;
+  // the work index is wave-uniform, so the descriptor below is read once
+  // with scalar loads and kept in registers (a reference into global memory
+  // would be re-read after every store the compiler cannot disambiguate)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
   float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
   for (int i = br.begin + blockIdx.x * C::kWaves + wave; i < br.end; i += gridDim.x * C::kWaves) {
-    const int im = find_img(br.prefix, br.nimg, i);
-    const ImgDesc& d = br.ds[im];
+    const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
+    const ImgDesc d = ldc(br.ds + im);
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
@@ -986,7 +1014,7 @@ __global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) k_filter(ImgDesc d
 __global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br) {
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
     const int im = find_img(br.prefix, br.nimg, i);
-    const ImgDesc& d = br.ds[im];
+    const ImgDesc d = ldc(br.ds + im);  // by value: kept in registers
     const int j = i - br.prefix[im];
     if (stage == STAGE_PREP) prep_chunk(d, j);
     else if (stage == STAGE_AGG1) agg1_chunk(d, j);
@@ -1000,7 +1028,7 @@ __global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
     const int im = find_img(br.prefix, br.nimg, i);
-    const ImgDesc& d = br.ds[im];
+    const ImgDesc d = ldc(br.ds + im);  // by value: kept in registers
     const int j = i - br.prefix[im];
     const int nbx = (d.nc + 3) / 4;
     if (STEP == 1) match1_block(d, kp, j / nbx, j % nbx, smem);
