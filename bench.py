@@ -333,15 +333,15 @@ def main():
     i2 = torch.empty((R, p.n_wie), dtype=torch.int32, device="cuda")
     c2 = torch.empty(R, dtype=torch.int32, device="cuda")
     num = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
-    den = torch.empty_like(num)
+    wsum = torch.empty_like(num)
     basic = torch.empty_like(num)
     for im in imgs:
         bm3d.prepare(im, planar, lum)
         bm3d.block_match(lum, 1, p, i1, c1)
         num.zero_()
-        den.zero_()
-        bm3d.collab_filter(planar, None, sigma, 1, i1, c1, p, num, den)
-        bm3d.aggregate(num, den, False, basic)
+        wsum.zero_()
+        bm3d.collab_filter(planar, None, sigma, 1, i1, c1, p, num, wsum)
+        bm3d.aggregate(num, wsum, False, p, basic)
         bm3d.luminance(basic, lumf)
         bm3d.block_match(lumf, 2, p, i2, c2)
         wm = work_models(H, W, S, c1.cpu().numpy(), c2.cpu().numpy())

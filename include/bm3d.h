@@ -17,7 +17,7 @@
  * inside the image.
  *
  * Conventions for every entry point:
- *  - pointers named img/out/planar/lum/basic/num/den/idx/cnt are DEVICE
+ *  - pointers named img/out/planar/lum/basic/num/wsum/idx/cnt are DEVICE
  *    pointers owned by the caller; the library never frees them;
  *  - image layout: interleaved HWC uint8 input, planar [c][h][w] float
  *    working buffers, HWC float output on the [0,255] scale, unclipped;
@@ -115,23 +115,29 @@ int bm3d_prepare(const uint8_t* img, int h, int w, int c, float* planar, uint8_t
 int bm3d_block_match(const void* src, int src_is_f32, int h, int w, int step,
                      const bm3d_params* p, int32_t* idx, int32_t* cnt, bm3d_stream_t stream);
 
-/* Collaborative filtering of all groups, accumulated (+=) into num/den
+/* Collaborative filtering of all groups, accumulated (+=) into num/wsum
  * (planar float [c][h][w]).  noisy: planar working channels.  step 1: 3D
  * spectrum hard-thresholded at lambda*sigma (kept iff |s| > lambda*sigma),
  * group weight 1/N_kept (1 if none kept); basic must be NULL.  step 2:
  * empirical Wiener shrinkage W = B^2/(B^2+sigma^2) of the noisy spectrum, B
  * the spectrum of `basic` (planar) over the same patches, weight 1/sum W^2
- * (1 if 0).  Weights are per channel; each filtered patch adds
- * w*K(u)K(v)*value into num and w*K(u)K(v) into den (K = Kaiser window). */
+ * (1 if 0).  Weights are per channel; each filtered patch at top-left
+ * (y0, x0) adds w*K(u)*K(v)*value into num[y0+u][x0+v] (K = Kaiser window of
+ * p->kaiser_beta) and w into wsum[y0][x0].  The aggregation denominator of
+ * the method, sum of w*K(u)*K(v) over the patches covering a pixel, is wsum
+ * correlated with the 8x8 Kaiser window; bm3d_aggregate forms it. */
 int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int c,
                        float sigma, int step, const int32_t* idx, const int32_t* cnt,
-                       const bm3d_params* p, float* num, float* den, bm3d_stream_t stream);
+                       const bm3d_params* p, float* num, float* wsum, bm3d_stream_t stream);
 
-/* out = num/den.  final_step = 0: out is planar [c][h][w] (the basic
- * estimate).  final_step = 1: out is HWC [h][w][c], opponent channels mapped
- * back to RGB with the transpose of the opponent matrix. */
-int bm3d_aggregate(const float* num, const float* den, int h, int w, int c, int final_step,
-                   float* out, bm3d_stream_t stream);
+/* out = num/den with den[y][x] = sum over u,v in 0..7 (y-u, x-v >= 0) of
+ * wsum[y-u][x-v]*K(u)*K(v), K the Kaiser window of p->kaiser_beta (only that
+ * field of p is used; p must still pass validation).  final_step = 0: out is
+ * planar [c][h][w] (the basic estimate).  final_step = 1: out is HWC
+ * [h][w][c], opponent channels mapped back to RGB with the transpose of the
+ * opponent matrix. */
+int bm3d_aggregate(const float* num, const float* wsum, int h, int w, int c, int final_step,
+                   const bm3d_params* p, float* out, bm3d_stream_t stream);
 
 /* Step-2 matching luminance from a planar basic estimate: the grey channel,
  * or the first opponent channel / sqrt3 (= mean of R,G,B).  lum: float [h][w]. */

@@ -62,7 +62,7 @@ _SIGS = {
     "bm3d_prepare": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "bm3d_block_match": (_i, [_vp, _i, _i, _i, _i, _PP, _vp, _vp, _vp]),
     "bm3d_collab_filter": (_i, [_vp, _vp, _i, _i, _i, _f, _i, _vp, _vp, _PP, _vp, _vp, _vp]),
-    "bm3d_aggregate": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp]),
+    "bm3d_aggregate": (_i, [_vp, _vp, _i, _i, _i, _i, _PP, _vp, _vp]),
     "bm3d_luminance": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "bm3d_denoise": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
@@ -160,7 +160,7 @@ def block_match(src, step: int, p: Params, idx, cnt, stream=None):
                                  _stream(stream)), "bm3d_block_match")
 
 
-def collab_filter(noisy, basic, sigma: float, step: int, idx, cnt, p: Params, num, den,
+def collab_filter(noisy, basic, sigma: float, step: int, idx, cnt, p: Params, num, wsum,
                   stream=None):
     torch = _torch()
     c, h, w = noisy.shape
@@ -169,16 +169,16 @@ def collab_filter(noisy, basic, sigma: float, step: int, idx, cnt, p: Params, nu
                                    step, _ptr(idx, torch.int32, "idx"),
                                    _ptr(cnt, torch.int32, "cnt"), ctypes.byref(p),
                                    _ptr(num, torch.float32, "num"),
-                                   _ptr(den, torch.float32, "den"), _stream(stream)),
+                                   _ptr(wsum, torch.float32, "wsum"), _stream(stream)),
            "bm3d_collab_filter")
 
 
-def aggregate(num, den, final_step: bool, out, stream=None):
+def aggregate(num, wsum, final_step: bool, p: Params, out, stream=None):
     torch = _torch()
     c, h, w = num.shape
-    _check(_lib.bm3d_aggregate(_ptr(num, torch.float32, "num"), _ptr(den, torch.float32, "den"),
-                               h, w, c, 1 if final_step else 0, _ptr(out, torch.float32, "out"),
-                               _stream(stream)), "bm3d_aggregate")
+    _check(_lib.bm3d_aggregate(_ptr(num, torch.float32, "num"), _ptr(wsum, torch.float32, "wsum"),
+                               h, w, c, 1 if final_step else 0, ctypes.byref(p),
+                               _ptr(out, torch.float32, "out"), _stream(stream)), "bm3d_aggregate")
 
 
 def luminance(basic, lum, stream=None):

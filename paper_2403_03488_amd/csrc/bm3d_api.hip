@@ -117,7 +117,7 @@ int run(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s
 
 // workspace carve-up of one image
 struct Layout {
-  size_t planar, lum8, lumf, basic, num, den, idx1, cnt1, idx2, cnt2, total;
+  size_t planar, lum8, lumf, basic, num, wsum, idx1, cnt1, idx2, cnt2, total;
 };
 Layout layout(int h, int w, int c, const bm3d_params* p) {
   size_t hw = (size_t)h * w;
@@ -129,7 +129,7 @@ Layout layout(int h, int w, int c, const bm3d_params* p) {
   L.lumf = o;   o += align_up(hw * 4);
   L.basic = o;  o += align_up(c * hw * 4);
   L.num = o;    o += align_up(c * hw * 4);
-  L.den = o;    o += align_up(c * hw * 4);
+  L.wsum = o;   o += align_up(c * hw * 4);
   L.idx1 = o;   o += align_up(R * p->n_ht * 4);
   L.cnt1 = o;   o += align_up(R * 4);
   L.idx2 = o;   o += align_up(R * p->n_wie * 4);
@@ -144,7 +144,7 @@ void bind_workspace(ImgDesc& d, char* base, const Layout& L) {
   d.lumf = (float*)(base + L.lumf);
   d.basic = (float*)(base + L.basic);
   d.num = (float*)(base + L.num);
-  d.den = (float*)(base + L.den);
+  d.wsum = (float*)(base + L.wsum);
   d.idx1 = (int32_t*)(base + L.idx1);
   d.cnt1 = (int32_t*)(base + L.cnt1);
   d.idx2 = (int32_t*)(base + L.idx2);
@@ -229,13 +229,13 @@ extern "C" int bm3d_block_match(const void* src, int src_is_f32, int h, int w, i
 
 extern "C" int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int c,
                                   float sigma, int step, const int32_t* idx, const int32_t* cnt,
-                                  const bm3d_params* p, float* num, float* den,
+                                  const bm3d_params* p, float* num, float* wsum,
                                   bm3d_stream_t stream) {
   int e = check_image(h, w, c);
   if (e) return e;
   if ((e = check_params(p))) return e;
   if ((e = check_sigma(sigma))) return e;
-  if (!noisy || !idx || !cnt || !num || !den) return BM3D_ERR_ARG;
+  if (!noisy || !idx || !cnt || !num || !wsum) return BM3D_ERR_ARG;
   if (step == 1 ? basic != nullptr : (step != 2 || basic == nullptr)) return BM3D_ERR_ARG;
   ImgDesc d = base_desc(h, w, c, sigma, p);
   KParams kp = make_kparams(p);
@@ -243,7 +243,7 @@ extern "C" int bm3d_collab_filter(const float* noisy, const float* basic, int h,
   d.basic = (float*)basic;
   d.nkept = p->debug_nkept;
   d.num = num;
-  d.den = den;
+  d.wsum = wsum;
   if (step == 1) {
     d.idx1 = (int32_t*)idx;
     d.cnt1 = (int32_t*)cnt;
@@ -255,21 +255,23 @@ extern "C" int bm3d_collab_filter(const float* noisy, const float* basic, int h,
              want_sync(p));
 }
 
-extern "C" int bm3d_aggregate(const float* num, const float* den, int h, int w, int c,
-                              int final_step, float* out, bm3d_stream_t stream) {
+extern "C" int bm3d_aggregate(const float* num, const float* wsum, int h, int w, int c,
+                              int final_step, const bm3d_params* p, float* out,
+                              bm3d_stream_t stream) {
   int e = check_image(h, w, c);
   if (e) return e;
-  if (!num || !den || !out) return BM3D_ERR_ARG;
+  if ((e = check_params(p))) return e;
+  if (!num || !wsum || !out) return BM3D_ERR_ARG;
   ImgDesc d = base_desc(h, w, c, 0.f, nullptr);
   d.num = (float*)num;
-  d.den = (float*)den;
-  KParams kp{};
+  d.wsum = (float*)wsum;
+  KParams kp = make_kparams(p);
   if (final_step) {
     d.out = out;
-    return run(STAGE_AGG2, 0, d, kp, (hipStream_t)stream, false);
+    return run(STAGE_AGG2, 0, d, kp, (hipStream_t)stream, want_sync(p));
   }
   d.basic = out;
-  return run(STAGE_AGG1, 0, d, kp, (hipStream_t)stream, false);
+  return run(STAGE_AGG1, 0, d, kp, (hipStream_t)stream, want_sync(p));
 }
 
 extern "C" int bm3d_luminance(const float* basic, int h, int w, int c, float* lum,

@@ -47,7 +47,7 @@ struct ImgDesc {
   float* lumf;         // [h][w] step-2 matching luminance
   float* basic;        // [c][h][w] basic estimate
   float* num;          // [c][h][w] aggregation numerator
-  float* den;          // [c][h][w] aggregation denominator
+  float* wsum;         // [c][h][w] sum of group weights per patch position
   int32_t* idx1;       // [R][n_ht]
   int32_t* cnt1;       // [R]
   int32_t* idx2;       // [R][n_wie]
@@ -59,6 +59,12 @@ struct ImgDesc {
   uint32_t thr1;       // step-1 integer SSD bound floor(64 tau_ht), <= 2^22-1
   float thr2;          // step-2 SSD bound 64 tau_wie
 };
+
+// Aggregation tile (pixels): one 256-thread workgroup item.
+constexpr int kAggRows = 16, kAggCols = 64;
+__host__ __device__ inline int agg_items(int h, int w) {
+  return ((h + kAggRows - 1) / kAggRows) * ((w + kAggCols - 1) / kAggCols);
+}
 
 // Parameters shared by every image of a launch.
 struct KParams {

@@ -5,11 +5,12 @@
 //   match1    grouping on the uint8 luminance: exact integer SSDs from int8
 //             MFMA cross terms, wavefront top-N selection
 //   filter1   3D DCT (x) Walsh-Hadamard as a chain of MFMA products, hard
-//             threshold, inverse, Kaiser-weighted aggregation in LDS
-//   agg1      basic estimate = num/den, step-2 luminance
+//             threshold, inverse, Kaiser-weighted aggregation in LDS;
+//             group weights summed per patch position (wsum)
+//   agg1      basic estimate = num/den, den = wsum (x) Kaiser, step-2 luminance
 //   match2    grouping on the FP32 basic luminance (direct FP32 SSDs)
 //   filter2   Wiener shrinkage with the basic estimate as pilot
-//   agg2      final estimate = num/den, opponent -> RGB, HWC
+//   agg2      final estimate = num/den (same den), opponent -> RGB, HWC
 // Every stage exists as a single-image kernel (descriptor by value, one
 // workgroup per tile) and a batched kernel that walks a device work list of
 // (image, tile) items with a grid-stride loop (persistent when the grid is
@@ -65,22 +66,70 @@ __device__ void fill_chunk(const ImgDesc& d, int chunk) {
     size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
     if (p < n) {
       d.num[p] = 0.f;
-      d.den[p] = 0.f;
+      d.wsum[p] = 0.f;
     }
   }
 }
 
-// basic = num/den (planar); step-2 luminance (grey, or channel 0 / sqrt3)
-__device__ void agg1_chunk(const ImgDesc& d, int chunk) {
+// ============================================================ aggregation ==
+// An aggregation item is a kAggRows x kAggCols pixel tile (agg_items() per
+// image); thread t covers column t % 64 and rows 4 (t / 64) .. +3.  The
+// denominator at (y, x) is sum_{u,v < 8} wsum(y - u, x - v) K(u) K(v): the
+// per-position sums of group weights correlated with the Kaiser window,
+// formed separably in LDS from rows y0-7 .. y0+15 and columns x0-8 .. x0+63
+// of wsum (zero outside the image).
+struct AggLds {
+  float wt[kAggRows + 7][kAggCols + 8];  // wsum window
+  float hs[kAggRows + 7][kAggCols];      // its horizontal Kaiser sums
+};
+
+// num / den of channel ch at this thread's 4 pixels (0 outside the image)
+__device__ void agg_channel(const ImgDesc& d, const KParams& kp, int ch, int y0, int x0, AggLds& sh,
+                            float (&e)[4]) {
   const size_t hw = (size_t)d.h * d.w;
-  const size_t p0 = (size_t)chunk * kChunk;
+  const float* __restrict__ ws = d.wsum + ch * hw;
+  const int tid = threadIdx.x, xx = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < (kAggRows + 7) * (kAggCols + 8); i += kThreads) {
+    const int r = i / (kAggCols + 8), cc = i - r * (kAggCols + 8);
+    const int y = y0 - 7 + r, x = x0 - 8 + cc;
+    sh.wt[r][cc] = (y >= 0 && y < d.h && x >= 0 && x < d.w) ? ws[(size_t)y * d.w + x] : 0.f;
+  }
+  __syncthreads();
+  for (int r = wv; r < kAggRows + 7; r += kThreads / 64) {
+    float a = 0.f;
+#pragma unroll
+    for (int v = 0; v < 8; v++) a = __builtin_fmaf(kp.kaiser[v], sh.wt[r][xx + 8 - v], a);
+    sh.hs[r][xx] = a;
+  }
+  __syncthreads();
+#pragma unroll
   for (int k = 0; k < 4; k++) {
-    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
-    if (p >= hw) return;
-    for (int ch = 0; ch < d.c; ch++) {
-      float b = d.num[ch * hw + p] / d.den[ch * hw + p];
-      d.basic[ch * hw + p] = b;
-      if (ch == 0 && d.lumf) d.lumf[p] = d.c == 1 ? b : b * OPP_A;
+    const int yl = 4 * wv + k, y = y0 + yl, x = x0 + xx;
+    float den = 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; u++) den = __builtin_fmaf(kp.kaiser[u], sh.hs[yl + 7 - u][xx], den);
+    e[k] = (y < d.h && x < d.w) ? d.num[ch * hw + (size_t)y * d.w + x] / den : 0.f;
+  }
+  __syncthreads();  // the LDS is reused by the next channel / item
+}
+
+// step 1: basic estimate (planar) and the step-2 matching luminance
+__device__ void agg1_tile(const ImgDesc& d, const KParams& kp, int item, AggLds& sh) {
+  const size_t hw = (size_t)d.h * d.w;
+  const int ntx = (d.w + kAggCols - 1) / kAggCols;
+  const int y0 = (item / ntx) * kAggRows, x0 = (item % ntx) * kAggCols;
+  const int xx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int ch = 0; ch < d.c; ch++) {
+    float e[4];
+    agg_channel(d, kp, ch, y0, x0, sh, e);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int y = y0 + 4 * wv + k, x = x0 + xx;
+      if (y < d.h && x < d.w) {
+        const size_t p = (size_t)y * d.w + x;
+        d.basic[ch * hw + p] = e[k];
+        if (ch == 0 && d.lumf) d.lumf[p] = d.c == 1 ? e[k] : e[k] * OPP_A;
+      }
     }
   }
 }
@@ -97,22 +146,24 @@ __device__ void lum_chunk(const ImgDesc& d, int chunk) {
   }
 }
 
-// final = num/den, opponent -> RGB via the transpose, HWC
-__device__ void agg2_chunk(const ImgDesc& d, int chunk) {
-  const size_t hw = (size_t)d.h * d.w;
-  const size_t p0 = (size_t)chunk * kChunk;
+// step 2: final estimate, HWC, opponent channels mapped back to RGB
+__device__ void agg2_tile(const ImgDesc& d, const KParams& kp, int item, AggLds& sh) {
+  const int ntx = (d.w + kAggCols - 1) / kAggCols;
+  const int y0 = (item / ntx) * kAggRows, x0 = (item % ntx) * kAggCols;
+  const int xx = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float e[3][4];
+  for (int ch = 0; ch < d.c; ch++) agg_channel(d, kp, ch, y0, x0, sh, e[ch]);
+#pragma unroll
   for (int k = 0; k < 4; k++) {
-    size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
-    if (p >= hw) return;
+    const int y = y0 + 4 * wv + k, x = x0 + xx;
+    if (y >= d.h || x >= d.w) continue;
+    const size_t p = (size_t)y * d.w + x;
     if (d.c == 1) {
-      d.out[p] = d.num[p] / d.den[p];
+      d.out[p] = e[0][k];
     } else {
-      float e0 = d.num[p] / d.den[p];
-      float e1 = d.num[hw + p] / d.den[hw + p];
-      float e2 = d.num[2 * hw + p] / d.den[2 * hw + p];
-      d.out[3 * p] = OPP_A * e0 + OPP_B * e1 + OPP_C * e2;
-      d.out[3 * p + 1] = OPP_A * e0 - 2.f * OPP_C * e2;
-      d.out[3 * p + 2] = OPP_A * e0 - OPP_B * e1 + OPP_C * e2;
+      d.out[3 * p] = OPP_A * e[0][k] + OPP_B * e[1][k] + OPP_C * e[2][k];
+      d.out[3 * p + 1] = OPP_A * e[0][k] - 2.f * OPP_C * e[2][k];
+      d.out[3 * p + 2] = OPP_A * e[0][k] - OPP_B * e[1][k] + OPP_C * e[2][k];
     }
   }
 }
@@ -492,7 +543,7 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
 // ========================================================= collaborative ==
 // Each wave filters the groups of its own T x T tile of references and
 // aggregates them into a wave-private LDS accumulator covering the tile's
-// search region; the region is then added into num/den with one coalesced
+// search region; the region is then added into num with one coalesced
 // atomic per touched pixel.  A workgroup only shares the transform tables.
 //
 // Per group (n members, one channel), with the 16x16 fragments of
@@ -513,11 +564,14 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
 // small per-wave staging buffer, four members per step (coinciding addresses
 // within a step are merged in registers).  The denominator sum of w K(u)K(v)
 // over member placements equals the Kaiser window correlated with the
-// per-position sum of group weights, so only one add per member is made (the
-// weight map W) and den is formed at flush time.
+// per-position sum of group weights, so the filter adds each member's weight
+// once, at its corner, into a global weight map (wsum); the aggregation forms
+// the denominator from it.  Keeping no weight map in LDS leaves room for
+// 8 waves per CU with 16-bit operands (6 with FP32 operands, whose DCT
+// tables are twice as large).
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
-  static constexpr int kWaves = sizeof(frag) == 16 ? 4 : 6;  // waves per workgroup
+  static constexpr int kWaves = sizeof(frag) == 16 ? 6 : 8;  // waves per workgroup
   // staging row pitch: member rows 68 floats apart, so the 16 lanes of a
   // fragment row write to different LDS banks
   static constexpr int kSP = 68;
@@ -526,10 +580,9 @@ template <class XF> struct FilterCfg {
   // row pitch of the numerator region: = 8 (mod 16) so the 8 rows of a
   // member patch fall in different LDS banks
   static __host__ __device__ int pitch(int rw) { return rw + ((24 - rw % 16) % 16); }
-  static __host__ __device__ int rw(int S, int T) { return 3 * (T - 1) + S; }
-  // numerator region, weight map, staging [16][kSP], one spare slot per lane
+  // numerator region, staging [16][kSP], one spare slot per lane
   static __host__ __device__ size_t per_wave(int S, int T) {
-    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + (size_t)rw(S, T) * rw(S, T) + 16 * kSP + 64) * 4;
+    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + 16 * kSP + 64) * 4;
   }
   static __host__ __device__ size_t bytes(int S, int T) { return tables() + kWaves * per_wave(S, T); }
 };
@@ -597,7 +650,7 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
 template <int STEP, class XF>
 __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
                                  const typename XF::frag* __restrict__ tabB,
-                                 const typename XF::frag* __restrict__ tabA, float* wnum, float* wW) {
+                                 const typename XF::frag* __restrict__ tabA, float* wnum) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
   const int S = STEP == 1 ? kp.S1 : kp.S2;
@@ -612,11 +665,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, T, ty, tx);
   const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
   const int RP = C::pitch(RW);             // its row pitch
-  const int WW = g.nx;                     // weight map row pitch (positions)
-  float* wst = wW + C::rw(S, T) * C::rw(S, T);  // staging [16][kSP]
+  float* wst = wnum + C::rnum(S, T) * C::pitch(C::rnum(S, T));  // staging [16][kSP]
+  float* __restrict__ gwsum = d.wsum + ch * hw;
 
   for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
-  for (int i = l; i < g.ny * WW; i += 64) wW[i] = 0.f;
   wave_lds_sync();
 
   const float centre = channel_centre(d.c, ch);
@@ -847,10 +899,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int v = 0; v < 4; v++) add[v] = __builtin_fmaf(kc, Kv[v], acc[v]);
         *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
       }
-      if (q == 0 && mv[gt]) {
-        float* pw = wW + (my[gt] - g.uy0) * WW + (mx[gt] - g.ux0);
-        *pw = *pw + wgt;
-      }
+      if (q == 0 && mv[gt]) gadd(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
       wave_lds_sync();
       // four members per step (an absent member stages zeros at the region
       // corner); the writes go in member order, so where members coincide
@@ -883,53 +932,19 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     }
   }
 
-  // ---- flush: num as accumulated; den = weight map (x) Kaiser window,
-  // separably: each lane walks one region column down the rows, keeping the
-  // last 8 horizontal sums of the weight map in registers
+  // ---- flush: the region into num, four rows per iteration (all their LDS
+  // reads first); pixels no member touched hold exact zeros and are skipped
   float* gnum = d.num + ch * hw;
-  float* gden = d.den + ch * hw;
-  float kw[8];
-#pragma unroll
-  for (int i = 0; i < 8; i++) kw[i] = kp.kaiser[i];
   for (int x0 = 0; x0 < RW; x0 += 64) {
     const int x = x0 + l;
     const int xc = min(x, RW - 1);  // in-range address for lanes past the region
-    float hsum[8];
-#pragma unroll
-    for (int i = 0; i < 8; i++) hsum[i] = 0.f;
-    // four rows per iteration: all their LDS reads first, then the sums
     for (int y0 = 0; y0 < RH; y0 += 4) {
-      float wv[4][8], nv[4];
+      float nv[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int y = y0 + k;
-        const float* wr = wW + min(y, g.ny - 1) * WW;
+      for (int k = 0; k < 4; k++) nv[k] = wnum[min(y0 + k, RH - 1) * RP + xc];
 #pragma unroll
-        for (int v = 0; v < 8; v++) {
-          const int px = x - v;
-          const float t = wr[min(max(px, 0), g.nx - 1)];
-          wv[k][v] = (y < g.ny && px >= 0 && px < g.nx) ? t : 0.f;
-        }
-        nv[k] = wnum[min(y, RH - 1) * RP + xc];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int y = y0 + k;
-#pragma unroll
-        for (int i = 7; i > 0; i--) hsum[i] = hsum[i - 1];
-        float hsv = 0.f;
-#pragma unroll
-        for (int v = 0; v < 8; v++) hsv += kw[v] * wv[k][v];
-        hsum[0] = hsv;
-        float dv = 0.f;
-#pragma unroll
-        for (int u = 0; u < 8; u++) dv += kw[u] * hsum[u];
-        if (y < RH && x < RW && dv != 0.f) {
-          size_t o = (size_t)(g.uy0 + y) * w + g.ux0 + x;
-          gadd(gnum + o, nv[k]);
-          gadd(gden + o, dv);
-        }
-      }
+      for (int k = 0; k < 4; k++)
+        if (y0 + k < RH && x < RW && nv[k] != 0.f) gadd(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
     }
   }
   wave_lds_sync();
@@ -948,10 +963,9 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int wave = threadIdx.x >> 6;
   float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
-  float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
   const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
   const int t = blockIdx.x * C::kWaves + wave;
-  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wnum, wW);
+  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wnum);
 }
 
 // image holding global item i: largest k with prefix[k] <= i
@@ -979,22 +993,27 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   // would be re-read after every store the compiler cannot disambiguate)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
-  float* wW = wnum + C::rnum(S, kp.tile) * C::pitch(C::rnum(S, kp.tile));
   for (int i = br.begin + blockIdx.x * C::kWaves + wave; i < br.end; i += gridDim.x * C::kWaves) {
     const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
     const ImgDesc d = ldc(br.ds + im);
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
-    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wnum, wW);
+    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wnum);
   }
 }
 
 // ================================================================ kernels ==
 __global__ void __launch_bounds__(kThreads) k_prep(ImgDesc d) { prep_chunk(d, blockIdx.x); }
 __global__ void __launch_bounds__(kThreads) k_fill(ImgDesc d) { fill_chunk(d, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_agg1(ImgDesc d) { agg1_chunk(d, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_agg2(ImgDesc d) { agg2_chunk(d, blockIdx.x); }
+__global__ void __launch_bounds__(kThreads) k_agg1(ImgDesc d, KParams kp) {
+  __shared__ AggLds sh;
+  agg1_tile(d, kp, blockIdx.x, sh);
+}
+__global__ void __launch_bounds__(kThreads) k_agg2(ImgDesc d, KParams kp) {
+  __shared__ AggLds sh;
+  agg2_tile(d, kp, blockIdx.x, sh);
+}
 __global__ void __launch_bounds__(kThreads) k_lum(ImgDesc d) { lum_chunk(d, blockIdx.x); }
 __global__ void __launch_bounds__(kThreads) k_match1(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
@@ -1011,14 +1030,15 @@ __global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) k_filter(ImgDesc d
 }
 
 // batched: each workgroup walks items begin + blockIdx.x, += gridDim.x
-__global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br) {
+__global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br, KParams kp) {
+  __shared__ AggLds sh;  // aggregation stages only
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
     const int im = find_img(br.prefix, br.nimg, i);
     const ImgDesc d = ldc(br.ds + im);  // by value: kept in registers
     const int j = i - br.prefix[im];
     if (stage == STAGE_PREP) prep_chunk(d, j);
-    else if (stage == STAGE_AGG1) agg1_chunk(d, j);
-    else if (stage == STAGE_AGG2) agg2_chunk(d, j);
+    else if (stage == STAGE_AGG1) agg1_tile(d, kp, j, sh);
+    else if (stage == STAGE_AGG2) agg2_tile(d, kp, j, sh);
     else if (stage == STAGE_FILL) fill_chunk(d, j);
     else lum_chunk(d, j);
   }
@@ -1067,10 +1087,10 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
       hipLaunchKernelGGL(k_fill, dim3(elem_blocks(d, true)), dim3(kThreads), 0, s, d);
       break;
     case STAGE_AGG1:
-      hipLaunchKernelGGL(k_agg1, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      hipLaunchKernelGGL(k_agg1, dim3(agg_items(d.h, d.w)), dim3(kThreads), 0, s, d, kp);
       break;
     case STAGE_AGG2:
-      hipLaunchKernelGGL(k_agg2, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
+      hipLaunchKernelGGL(k_agg2, dim3(agg_items(d.h, d.w)), dim3(kThreads), 0, s, d, kp);
       break;
     case STAGE_LUM:
       hipLaunchKernelGGL(k_lum, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
@@ -1128,7 +1148,7 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
     case STAGE_AGG2:
     case STAGE_FILL:
     case STAGE_LUM:
-      hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, br);
+      hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, br, kp);
       break;
     case STAGE_MATCH1: {
       size_t b = match1_lds_bytes(kp.S1);

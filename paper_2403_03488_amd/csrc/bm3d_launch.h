@@ -23,11 +23,12 @@ enum Stage {
 // number of items of a stage is a function of its size (elementwise chunks,
 // 4x4-reference matching blocks, or channel x filter tiles), so a launch only
 // needs the image descriptors and the per-image prefix counts.
-enum ListKind { LIST_PIX = 0, LIST_PLANE = 1, LIST_MATCH = 2, LIST_FILTER = 3, LIST_KINDS = 4 };
+enum ListKind { LIST_PIX = 0, LIST_PLANE = 1, LIST_MATCH = 2, LIST_FILTER = 3, LIST_AGG = 4, LIST_KINDS = 5 };
 
 __host__ __device__ inline int list_of_stage(int stage) {
   switch (stage) {
-    case STAGE_PREP: case STAGE_AGG1: case STAGE_AGG2: case STAGE_LUM: return LIST_PIX;
+    case STAGE_PREP: case STAGE_LUM: return LIST_PIX;
+    case STAGE_AGG1: case STAGE_AGG2: return LIST_AGG;
     case STAGE_FILL: return LIST_PLANE;
     case STAGE_MATCH1: case STAGE_MATCH2: return LIST_MATCH;
     default: return LIST_FILTER;
@@ -40,6 +41,7 @@ __host__ __device__ inline int items_of(int list, const ImgDesc& d, int tile, in
     case LIST_PIX: return (int)((hw + chunk - 1) / chunk);
     case LIST_PLANE: return (int)((hw * d.c + chunk - 1) / chunk);
     case LIST_MATCH: return ((d.nr + 3) / 4) * ((d.nc + 3) / 4);
+    case LIST_AGG: return agg_items(d.h, d.w);
     default: return d.c * ((d.nr + tile - 1) / tile) * ((d.nc + tile - 1) / tile);
   }
 }

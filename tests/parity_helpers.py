@@ -45,6 +45,22 @@ def groups_touching(idx, cnt, mask, h, w):
     return (hit & valid).any(axis=1)
 
 
+def kaiser_den(wsum, beta):
+    """Aggregation denominator from per-position weight sums (FP64):
+    den[k, y, x] = sum over u, v < 8 of wsum[k, y-u, x-v] K[u] K[v], with K
+    numpy's Kaiser window.  The filters report weights this way; summing
+    w K(u) K(v) over the 64 pixels of every aggregated patch gives the same
+    denominator."""
+    K = np.kaiser(8, beta)
+    ws = np.asarray(wsum, np.float64)
+    _, h, w = ws.shape
+    den = np.zeros_like(ws)
+    for u in range(8):
+        for v in range(8):
+            den[:, u:, v:] += K[u] * K[v] * ws[:, :h - u, :w - v]
+    return den
+
+
 def all_patches(plane):
     h, w = plane.shape
     return sliding_window_view(np.asarray(plane, np.float64), (8, 8)).reshape(h - 7, w - 7, 64)

@@ -96,7 +96,8 @@ def test_host_validation_rejects_before_enqueue(B):
                                 None) == -1  # step 1 takes no basic estimate
     assert L.bm3d_collab_filter(fake, None, 64, 64, 1, 25.0, 2, fake, fake, ref(p), fake, fake,
                                 None) == -1  # step 2 needs one
-    assert L.bm3d_aggregate(fake, None, 64, 64, 1, 1, fake, None) == -1
+    assert L.bm3d_aggregate(fake, None, 64, 64, 1, 1, ref(p), fake, None) == -1
+    assert L.bm3d_aggregate(fake, fake, 64, 64, 1, 1, None, fake, None) == -1
     assert L.bm3d_prepare(fake, 64, 64, 4, fake, fake, None) == -1
     assert L.bm3d_luminance(None, 64, 64, 1, fake, None) == -1
     # batch plans

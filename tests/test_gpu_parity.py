@@ -111,17 +111,22 @@ def filter1_compare(B, img, sigma, S, xform=0):
     oi, oc = oracle.match_u8(lum, S, p.n_ht, float(p.tau_ht))
     onum, oden, margin, onk = oracle.collab_filter(planar, None, sigma, 1, oi, oc, op, want_margin=True)
     num = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
-    den = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
+    wsum = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
     gnk = torch.full((c, len(oc)), -1, dtype=torch.int32, device="cuda")
     p.debug_nkept = gnk.data_ptr()
-    B.collab_filter(dev(planar.astype(np.float32)), None, sigma, 1, dev(oi), dev(oc), p, num, den)
-    gnum, gden = host(num), host(den)
+    B.collab_filter(dev(planar.astype(np.float32)), None, sigma, 1, dev(oi), dev(oc), p, num, wsum)
+    basic = torch.empty((c, h, w), dtype=torch.float32, device="cuda")
+    B.aggregate(num, wsum, False, p, basic)
+    gws = host(wsum)
+    # weights sit at patch corners only
+    assert not gws[:, h - 7:, :].any() and not gws[:, :, w - 7:].any()
+    gden = ph.kaiser_den(gws, p.kaiser_beta)
     flips = (host(gnk) != onk).any(axis=0)
     # every threshold decision that differs must sit within rounding of lambda*sigma
     assert np.all(margin[flips] < ph.HT_MARGIN), margin[flips]
     taint = ph.patch_cover(oi, oc, flips, h, w)
     ok = ~taint
-    gb, ob = gnum / gden, onum / oden
+    gb, ob = host(basic), onum / oden
     err = np.abs(gb - ob)[:, ok]
     log("filter1 %s: groups with a differing threshold decision %d of %d (%.3f%% px), "
         "max|basic diff| %.2e (rest), %.2e (all)" %
@@ -195,9 +200,12 @@ def test_filter2_fp32(B, which):
     onum, oden = oracle.collab_filter(planar, basic32.astype(np.float64), 25.0, 2, oi, oc, op)
     c, h, w = planar.shape
     num = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
-    den = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
-    B.collab_filter(dev(planar.astype(np.float32)), dev(basic32), 25.0, 2, dev(oi), dev(oc), p, num, den)
-    g, o = host(num) / host(den), onum / oden
+    wsum = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
+    B.collab_filter(dev(planar.astype(np.float32)), dev(basic32), 25.0, 2, dev(oi), dev(oc), p, num, wsum)
+    est = torch.empty((c, h, w), dtype=torch.float32, device="cuda")
+    B.aggregate(num, wsum, False, p, est)
+    g, o = host(est), onum / oden
+    np.testing.assert_allclose(ph.kaiser_den(host(wsum), p.kaiser_beta), oden, rtol=1e-5)
     log("filter2 %s: max|diff| %.2e" % (which, np.abs(g - o).max()))
     assert np.abs(g - o).max() <= ph.FP32_TOL
 
@@ -206,21 +214,23 @@ def test_filter2_fp32(B, which):
 
 @pytest.mark.parametrize("c", [1, 3])
 def test_aggregate(B, c):
+    # shapes that leave partial 16 x 64 aggregation tiles in both directions
     rng = np.random.default_rng(c)
-    num = rng.uniform(-100, 300, (c, 33, 47))
-    den = rng.uniform(0.5, 3, (c, 33, 47))
-    gnum, gden = dev(num.astype(np.float32)), dev(den.astype(np.float32))
-    out = torch.empty((33, 47, c) if c == 3 else (c, 33, 47), dtype=torch.float32, device="cuda")
-    B.aggregate(gnum, gden, True, out)
-    ref = oracle.aggregate(num.astype(np.float32).astype(np.float64),
-                           den.astype(np.float32).astype(np.float64), True)
-    np.testing.assert_allclose(host(out).reshape(ref.shape), ref, atol=1e-4)
-    basic = torch.empty((c, 33, 47), dtype=torch.float32, device="cuda")
-    B.aggregate(gnum, gden, False, basic)
-    np.testing.assert_allclose(host(basic), oracle.aggregate(num.astype(np.float32).astype(np.float64),
-                                                             den.astype(np.float32).astype(np.float64),
-                                                             False), atol=1e-4)
-    lum = torch.empty((33, 47), dtype=torch.float32, device="cuda")
+    num = rng.uniform(-100, 300, (c, 33, 147)).astype(np.float32)
+    wsum = rng.uniform(0.05, 1, (c, 33, 147)).astype(np.float32)
+    p = gparams(B, 25.0, 16)
+    den = ph.kaiser_den(wsum, p.kaiser_beta)
+    gnum, gws = dev(num), dev(wsum)
+    out = torch.empty((33, 147, c) if c == 3 else (c, 33, 147), dtype=torch.float32, device="cuda")
+    B.aggregate(gnum, gws, True, p, out)
+    ref = oracle.aggregate(num.astype(np.float64), den, True)
+    # FP32 denominator (two 8-term FMA chains) and division: relative error ~1e-6
+    np.testing.assert_allclose(host(out).reshape(ref.shape), ref, rtol=1e-5, atol=1e-4)
+    basic = torch.empty((c, 33, 147), dtype=torch.float32, device="cuda")
+    B.aggregate(gnum, gws, False, p, basic)
+    np.testing.assert_allclose(host(basic), oracle.aggregate(num.astype(np.float64), den, False),
+                               rtol=1e-5, atol=1e-4)
+    lum = torch.empty((33, 147), dtype=torch.float32, device="cuda")
     B.luminance(basic, lum)
     np.testing.assert_allclose(host(lum), oracle.luminance(host(basic).astype(np.float64)), atol=1e-4)
 
@@ -242,15 +252,15 @@ def gpu_chain_with_idx2(B, img, sigma, p, idx2, cnt2):
     c1 = torch.empty(R, dtype=torch.int32, device="cuda")
     B.block_match(lum, 1, p, i1, c1)
     num = torch.zeros((c, h, w), dtype=torch.float32, device="cuda")
-    den = torch.zeros_like(num)
-    B.collab_filter(planar, None, sigma, 1, i1, c1, p, num, den)
+    wsum = torch.zeros_like(num)
+    B.collab_filter(planar, None, sigma, 1, i1, c1, p, num, wsum)
     basic = torch.empty_like(num)
-    B.aggregate(num, den, False, basic)
+    B.aggregate(num, wsum, False, p, basic)
     num.zero_()
-    den.zero_()
-    B.collab_filter(planar, basic, sigma, 2, dev(idx2), dev(cnt2), p, num, den)
+    wsum.zero_()
+    B.collab_filter(planar, basic, sigma, 2, dev(idx2), dev(cnt2), p, num, wsum)
     out = torch.empty(img.shape, dtype=torch.float32, device="cuda")
-    B.aggregate(num, den, True, out)
+    B.aggregate(num, wsum, True, p, out)
     return host(out), host(i1), host(c1), host(gnk)
 
 
