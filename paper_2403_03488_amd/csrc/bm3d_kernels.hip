@@ -454,7 +454,7 @@ __host__ __device__ inline size_t match2_lds_bytes(int S, int nwaves) {
 __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
   const int S = kp.S2, nmax = kp.n2;
   const int h = d.h, w = d.w;
-  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6;
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
   const int SH = g.SH, SW = g.SW, SS = SH * SW;
   const int RR = g.ny + 7;
@@ -479,25 +479,46 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
   }
   __syncthreads();
 
+  // Wave b takes the block's reference column b (kThreads = 256: four
+  // waves, four columns).  Lane l covers window row l/2 and 16 adjacent
+  // window columns.  The distance is a sum of 8 row distances; references
+  // of one column whose vertical windows sit at the same offset (all but
+  // those clamped at the top or bottom image border) pair each image row
+  // with the same candidate row, so each row's 16 row distances are formed
+  // once and added into every reference whose patch covers that row.
+  static_assert(kThreads == 256, "one wave per reference column of a 4 x 4 block");
+  const int b = wave;
+  if (b >= g.nci) return;
   const int wyy = l >> 1, wxx0 = (l & 1) * 16;
   const bool lane_ok = wyy < SH && wxx0 < SW;
   const float thr = d.thr2;
-  for (int m = wave; m < 16; m += nwaves) {
-    int a = m >> 2, b = m & 3;
-    if (a >= g.nri || b >= g.nci) continue;
-    int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
-    window_1d(ry, h, S, wy, t0);
-    window_1d(rx, w, S, wx, t0);
-    const int ryr = ry - g.uy0, rxr = rx - g.ux0, wyr = wy - g.uy0, wxr = wx - g.ux0;
-    float acc[16];
+  const int rx = ref_pos(g.ci0 + b, w);
+  int wx, t0;
+  window_1d(rx, w, S, wx, t0);
+  const int rxr = rx - g.ux0, wxr = wx - g.ux0;
+  const int na = g.nri;
+  int ry[4], wy[4];
+  bool shared = true;
 #pragma unroll
-    for (int c = 0; c < 16; c++) acc[c] = 0.f;
-    for (int u = 0; u < kP; u++) {
-      float P[8], rw[23];
+  for (int a = 0; a < 4; a++) {  // rows past the block repeat its last reference
+    ry[a] = ref_pos(g.ri0 + min(a, na - 1), h);
+    window_1d(ry[a], h, S, wy[a], t0);
+    shared = shared && wy[a] - ry[a] == wy[0] - ry[0];
+  }
+  float acc[4][16];
 #pragma unroll
-      for (int v = 0; v < 8; v++) P[v] = reg[(ryr + u) * kM2Pitch + rxr + v];
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 16; c++) acc[a][c] = 0.f;
+  // rows ya..yb of the image against candidate rows y + dyo + wyy, added
+  // into the references of amask that cover them
+  auto rows = [&](int ya, int yb, int dyo, int amask) {
+    for (int y = ya; y <= yb; y++) {
+      float P[8], rw[23], rs[16];
+#pragma unroll
+      for (int v = 0; v < 8; v++) P[v] = reg[(y - g.uy0) * kM2Pitch + rxr + v];
       if (lane_ok) {
-        const float* src = reg + (wyr + wyy + u) * kM2Pitch + wxr + wxx0;
+        const float* src = reg + (y + dyo + wyy - g.uy0) * kM2Pitch + wxr + wxx0;
 #pragma unroll
         for (int i = 0; i < 23; i++) rw[i] = src[i];
       } else {
@@ -506,20 +527,40 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
       }
 #pragma unroll
       for (int c = 0; c < 16; c++) {
+        float e = P[0] - rw[c];
+        rs[c] = e * e;
 #pragma unroll
-        for (int v = 0; v < 8; v++) {
-          float e = P[v] - rw[c + v];
-          acc[c] = __builtin_fmaf(e, e, acc[c]);
+        for (int v = 1; v < 8; v++) {
+          e = P[v] - rw[c + v];
+          rs[c] = __builtin_fmaf(e, e, rs[c]);
         }
       }
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+        if (((amask >> a) & 1) && y >= ry[a] && y < ry[a] + kP) {
+#pragma unroll
+          for (int c = 0; c < 16; c++) acc[a][c] += rs[c];
+        }
     }
+  };
+  if (shared) {
+    rows(ry[0], ry[na - 1] + kP - 1, wy[0] - ry[0], 0xF);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+      if (a < na) rows(ry[a], ry[a] + kP - 1, wy[a] - ry[a], 1 << a);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    if (a >= na) break;
+    const int ryr = ry[a] - g.uy0, wyr = wy[a] - g.uy0;
     uint32_t db[16], wi[16];
 #pragma unroll
     for (int c = 0; c < 16; c++) {
       int wxx = wxx0 + c;
       bool isref = (wyr + wyy == ryr) && (wxr + wxx == rxr);
-      bool ok = lane_ok && wxx < SW && !isref && acc[c] <= thr;
-      db[c] = ok ? __float_as_uint(acc[c]) : kNone32;
+      bool ok = lane_ok && wxx < SW && !isref && acc[a][c] <= thr;
+      db[c] = ok ? __float_as_uint(acc[a][c]) : kNone32;
       wi[c] = (uint32_t)(wyy * SW + wxx);
     }
     uint64_t sel;
@@ -527,14 +568,14 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx2 + r * nmax;
     if (l == 0) {
-      stg(o, ry * w + rx);
+      stg(o, ry[a] * w + rx);
       stg(d.cnt2 + r, n);
     }
     if (l + 1 < nmax) {
       int gi = -1;
       if (l < n - 1) {
         int widx = (int)(sel & 1023u);
-        gi = (wy + widx / SW) * w + wx + widx % SW;
+        gi = (wy[a] + widx / SW) * w + wx + widx % SW;
       }
       stg(o + l + 1, gi);
     }
