@@ -758,8 +758,11 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     // group size and everything derived from it are wave-uniform
     const int n = __builtin_amdgcn_readfirstlane(min(max(cnt_j, 1), nmax));
     const int NG = n > 16 ? 2 : 1;
-    const float rsn = n == 1 ? 1.f : n == 2 ? 0.70710678118654752f : n == 4 ? 0.5f
-                    : n == 8 ? 0.35355339059327376f : n == 16 ? 0.25f : 0.17677669529663688f;
+    // the spectra are kept as H.D1 (the orthonormal WHT times sqrt n): the
+    // threshold, the Wiener noise power and the inverse scale absorb sqrt n
+    const float sqn = n == 1 ? 1.f : n == 2 ? 1.41421356237309505f : n == 4 ? 2.f
+                    : n == 8 ? 2.82842712474619010f : n == 16 ? 4.f : 5.65685424949238020f;
+    const float rn = 1.f / (float)n;  // exact (n is a power of two)
     int my[2], mx[2];
     bool mv[2];
 #pragma unroll
@@ -831,16 +834,17 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int nt = 0; nt < 4; nt++) {
           const f32x4 acc = NG == 2 ? XF::mma2(Hf[tt][0], Hf[tt][1], XF::cvt(D1[0][nt]), XF::cvt(D1[1][nt]), zero4())
                                     : XF::mma(Hf[tt][0], XF::cvt(D1[0][nt]), zero4());
-          if (src_i == 0) D2[tt][nt] = acc * rsn;
-          else D2b[tt][nt] = acc * rsn;
+          if (src_i == 0) D2[tt][nt] = acc;
+          else D2b[tt][nt] = acc;
         }
       }
     }
 
     // ---- shrinkage.  Spectra rows t >= n are exactly zero (the Hadamard
     // blocks vanish there), so they are never kept and get zero gain unless
-    // sigma = 0.  The centre only moves the 3-D DC, restored around this.
-    const float off = 8.f * centre * sqrtf((float)n);
+    // sigma = 0.  The centre only moves the 3-D DC, restored around this
+    // (8 centre sqrt n in the orthonormal spectrum, times sqrt n here).
+    const float off = 8.f * centre * (float)n;
     if (l == 0) {
       D2[0][0][0] += off;
       if (STEP == 2) D2b[0][0][0] += off;
@@ -848,6 +852,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     float wgt;
     if (STEP == 1) {
       int kept = 0;
+      const float thr_n = thr * sqn;  // |c| > lambda sigma in the orthonormal spectrum
 #pragma unroll
       for (int tt = 0; tt < 2; tt++) {
         if (tt >= NG) break;
@@ -855,7 +860,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int nt = 0; nt < 4; nt++)
 #pragma unroll
           for (int v = 0; v < 4; v++) {
-            const bool keep = fabsf(D2[tt][nt][v]) > thr;
+            const bool keep = fabsf(D2[tt][nt][v]) > thr_n;
             kept += __popcll(__ballot(keep));
             D2[tt][nt][v] = keep ? D2[tt][nt][v] : 0.f;
           }
@@ -864,6 +869,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       wgt = kept >= 1 ? 1.f / (float)kept : 1.f;
     } else {
       float sw2 = 0.f;
+      const float sig2_n = sig2 * (float)n;  // B^2 / (B^2 + sigma^2), both sides times n
       if (sig2 > 0.f) {
 #pragma unroll
         for (int tt = 0; tt < 2; tt++) {
@@ -873,7 +879,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
             for (int v = 0; v < 4; v++) {
               const float b2 = D2b[tt][nt][v] * D2b[tt][nt][v];
-              const float W = b2 * __builtin_amdgcn_rcpf(b2 + sig2);
+              const float W = b2 * __builtin_amdgcn_rcpf(b2 + sig2_n);
               sw2 += W * W;
               D2[tt][nt][v] *= W;
             }
@@ -914,7 +920,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         if (gt >= NG) break;
         const f32x4 acc = NG == 2 ? XF::mma2(XF::cvt(D2[0][ct]), XF::cvt(D2[1][ct]), Hf[gt][0], Hf[gt][1], zero4())
                                   : XF::mma(XF::cvt(D2[0][ct]), Hf[gt][0], zero4());
-        D3[ct][gt] = acc * (rsn * wm[gt]);
+        D3[ct][gt] = acc * (rn * wm[gt]);
       }
     }
     // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
@@ -961,12 +967,16 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         }
 #pragma unroll
         for (int i = 0; i < 4; i++) o[i] = wnum[a[i]];
+        // a member coinciding with earlier ones of the step continues from
+        // the latest of their new values
+        float t[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          float t = o[i] + sv[i];
+          float base = o[i];
 #pragma unroll
-          for (int k = 0; k < i; k++) t += a[k] == a[i] ? sv[k] : 0.f;
-          wnum[a[i]] = t;
+          for (int k = 0; k < i; k++) base = a[k] == a[i] ? t[k] : base;
+          t[i] = base + sv[i];
+          wnum[a[i]] = t[i];
         }
       }
       wave_lds_sync();
