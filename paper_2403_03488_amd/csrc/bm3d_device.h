@@ -242,6 +242,36 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Upper bound of the k-th smallest (k >= 1) of the NV x 64 values v of the
+// wave, exact in the bits above LO (those below are returned set, so at
+// least k values are <= the result).  Radix descent: bit by bit from the top,
+// a bit of the k-th smallest is 0 iff at least k values are <= the largest
+// number with the bits found so far and a 0 there.  NV vector compares per
+// bit; the counts and the prefix stay on the scalar unit.
+template <int LO, int NV> __device__ inline uint32_t wave_kth_u32(const uint32_t (&v)[NV], int k) {
+  uint32_t prefix = 0;
+#pragma unroll
+  for (int bit = 31; bit >= LO; bit--) {
+    const uint32_t t = prefix | ((1u << bit) - 1u);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NV; i++) c += __popcll(__ballot(v[i] <= t));
+    prefix = c < k ? prefix | (1u << bit) : prefix;
+  }
+  return prefix | ((1u << LO) - 1u);
+}
+
+// The two smallest of a lane's 16 keys (duplicates allowed)
+template <class K> __device__ inline void two_smallest(const K (&k)[16], K& m1, K& m2) {
+  m1 = kmin(k[0], k[1]);
+  m2 = kmax(k[0], k[1]);
+#pragma unroll
+  for (int t = 2; t < 16; t++) {
+    m2 = kmin(m2, kmax(m1, k[t]));
+    m1 = kmin(m1, k[t]);
+  }
+}
+
 // Group selection shared by both matching steps, for NR references at once
 // (their dependency chains interleave).  Each lane holds 16 keys per
 // reference (all ones = not a candidate); keys order candidates by
@@ -252,9 +282,12 @@ __device__ inline void wave_lds_sync() {
 template <class K, int NR>
 __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR], K (&sel)[NR],
                              int (&n)[NR]) {
+  static_assert(sizeof(K) == 4, "keys are distance << 10 | window index");
   const K NONE = ~(K)0;
   const int l = lane_id();
-  K mn[NR];
+  K theta[NR];
+  int base[NR];
+  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < NR; r++) {
     int npass = 0;
@@ -262,19 +295,14 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
     for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[r][t] != NONE));
     const int m = 1 + npass < nmax ? 1 + npass : nmax;
     n[r] = 1 << (31 - __clz(m));
-    mn[r] = k[r][0];
+    // Upper bound on the (n-1)-th smallest key: the (n-1)-th smallest of the
+    // lane minima (n-1 distinct candidates lie at or below it), exact in the
+    // distance bits.  The callers spread window-adjacent candidates over
+    // lanes, so one minimum per lane already bounds tightly.
+    uint32_t mn[1] = {k[r][0]};
 #pragma unroll
-    for (int t = 1; t < 16; t++) mn[r] = kmin(mn[r], k[r][t]);
-  }
-  // Upper bound on the (n-1)-th smallest key: the (n-1)-th smallest of the
-  // per-lane minima (those are n-1 distinct candidates at or below it).
-  wave_sort_n<K, NR>(mn);
-  K theta[NR];
-  int base[NR];
-  const uint64_t lt = lanemask_lt();
-#pragma unroll
-  for (int r = 0; r < NR; r++) {
-    theta[r] = n[r] > 1 ? lane_value<K>(mn[r], n[r] - 2) : (K)0;
+    for (int t = 1; t < 16; t++) mn[0] = kmin(mn[0], k[r][t]);
+    theta[r] = n[r] > 1 ? wave_kth_u32<10, 1>(mn, n[r] - 1) : (K)0;
     base[r] = 0;
   }
   // compact the survivors (candidates with key <= theta) into buf
@@ -313,11 +341,12 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
 // Step-2 variant on FP32 distances.  db[t] = bit pattern of a non-negative
 // distance (~0u = not a candidate), wi[t] = its window index; the order is
 // (distance, window index) as 64-bit keys (bits << 32 | index).  The bound
-// theta is taken on 32-bit keys whose distance keeps only its top 22 bits
-// (monotone in the distance), and every candidate whose truncated distance
-// does not exceed theta's survives: a candidate above it has n-1 others with
-// strictly smaller distances, so it cannot be among the n-1 smallest.  Only
-// the survivors are sorted on full 64-bit keys.  Result as select_group.
+// theta is taken on the distances' top 22 bits (monotone in the distance):
+// the (n-1)-th smallest among the lanes' two smallest truncated distances.
+// Every candidate whose truncated distance does not exceed theta survives: a
+// candidate above it has n-1 others with strictly smaller distances, so it
+// cannot be among the n-1 smallest.  Only the survivors are sorted on full
+// 64-bit keys.  Result as select_group.
 __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t (&wi)[16], int nmax,
                                        uint64_t* buf, uint64_t& sel) {
   const uint32_t NONE = ~0u;
@@ -330,10 +359,15 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t 
   sel = ~0ull;
   if (n == 1) return 1;
   const int want = n - 1;
-  uint32_t mn = NONE;
+  // bound on the truncated distances (top 22 bits): the want-th smallest of
+  // the lanes' two smallest (a lane holds 16 window-adjacent candidates,
+  // which are often similar), so at least want candidates survive
+  uint32_t tk[16];
 #pragma unroll
-  for (int t = 0; t < 16; t++) mn = kmin(mn, db[t] == NONE ? NONE : ((db[t] & ~0x3FFu) | wi[t]));
-  const uint32_t th = lane_value<uint32_t>(wave_sort(mn), want - 1) >> 10;
+  for (int t = 0; t < 16; t++) tk[t] = db[t] | 0x3FFu;
+  uint32_t m2[2];
+  two_smallest<uint32_t>(tk, m2[0], m2[1]);
+  const uint32_t th = wave_kth_u32<10, 2>(m2, want) >> 10;
   int base = 0;
   const uint64_t lt = lanemask_lt();
 #pragma unroll
