@@ -740,8 +740,12 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   frag Hf[2][2];  // Hadamard blocks of the current group size
   int hn = 0;
   const int nrefs = g.nri * g.nci;
-  // the group size and member slots of a reference are loaded one reference
-  // ahead (slots beyond the group hold -1 and are ignored below)
+  // A reference's group size and member slots are loaded two references
+  // ahead; its member positions (and in step 1 the pixels of its members)
+  // are formed and loaded while the previous reference is inverted and
+  // aggregated (slots beyond the group hold -1 and are ignored below).  Step
+  // 2 loads its pixels when it uses them: holding them across the
+  // aggregation would spill registers there.
   auto ref_of = [&](int j) { return (size_t)(g.ri0 + j / g.nci) * d.nc + g.ci0 + j % g.nci; };
   int cnt_nx = 0, gi_nx[2] = {-1, -1};
   auto prefetch = [&](int j) {
@@ -750,26 +754,16 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) gi_nx[gt] = ldg(idx + rn * nmax + (16 * gt + col < nmax ? 16 * gt + col : 0));
   };
-  if (nrefs > 0) prefetch(0);
-  for (int j = 0; j < nrefs; j++) {
-    const size_t r = ref_of(j);
-    const int cnt_j = cnt_nx, gi_j[2] = {gi_nx[0], gi_nx[1]};
-    if (j + 1 < nrefs) prefetch(j + 1);
+  int n_nx = 1, my_nx[2], mx_nx[2];
+  bool mv_nx[2];
+  f32x4 an[2][4];  // step 1: noisy member pixels of the next reference
+  auto stage = [&]() {
     // group size and everything derived from it are wave-uniform
-    const int n = __builtin_amdgcn_readfirstlane(min(max(cnt_j, 1), nmax));
-    const int NG = n > 16 ? 2 : 1;
-    // the spectra are kept as H.D1 (the orthonormal WHT times sqrt n): the
-    // threshold, the Wiener noise power and the inverse scale absorb sqrt n
-    const float sqn = n == 1 ? 1.f : n == 2 ? 1.41421356237309505f : n == 4 ? 2.f
-                    : n == 8 ? 2.82842712474619010f : n == 16 ? 4.f : 5.65685424949238020f;
-    const float rn = 1.f / (float)n;  // exact (n is a power of two)
-    int my[2], mx[2];
-    bool mv[2];
+    n_nx = __builtin_amdgcn_readfirstlane(min(max(cnt_nx, 1), nmax));
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) {
       int gm = 16 * gt + col;
-      mv[gt] = gt < NG && gm < n;
-      int gi = gi_j[gt];
+      int gi = gi_nx[gt];
       // gi / w through a float reciprocal, corrected by one either way
       int yy = (int)((float)gi * inv_w), xx = gi - yy * w;
       yy = xx < 0 ? yy - 1 : xx >= w ? yy + 1 : yy;
@@ -777,10 +771,39 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       // a member must lie in the tile's search region (true for any grouping
       // made with the same window rule); anything else is ignored
       bool inside = gi >= 0 && yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
-      mv[gt] = mv[gt] && inside;
-      my[gt] = inside ? yy : g.uy0;
-      mx[gt] = inside ? xx : g.ux0;
+      mv_nx[gt] = gm < n_nx && inside;
+      my_nx[gt] = inside ? yy : g.uy0;
+      mx_nx[gt] = inside ? xx : g.ux0;
     }
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      if (STEP == 2 || (gt == 1 && n_nx <= 16)) break;
+#pragma unroll
+      for (int kt = 0; kt < 4; kt++) {
+        const float* src = noisy + (size_t)(my_nx[gt] + 2 * kt + (q >> 1)) * w + mx_nx[gt] + 4 * (q & 1);
+#pragma unroll
+        for (int v = 0; v < 4; v++) an[gt][kt][v] = ldg(src + v);  // always a valid pixel
+      }
+    }
+  };
+  if (nrefs > 0) {
+    prefetch(0);
+    stage();
+    if (nrefs > 1) prefetch(1);
+  }
+  for (int j = 0; j < nrefs; j++) {
+    const size_t r = ref_of(j);
+    // the group size and everything derived from it are wave-uniform (kept
+    // in scalar registers: the transforms branch on them)
+    const int n = __builtin_amdgcn_readfirstlane(n_nx);
+    const int NG = n > 16 ? 2 : 1;
+    // the spectra are kept as H.D1 (the orthonormal WHT times sqrt n): the
+    // threshold, the Wiener noise power and the inverse scale absorb sqrt n
+    const float sqn = n == 1 ? 1.f : n == 2 ? 1.41421356237309505f : n == 4 ? 2.f
+                    : n == 8 ? 2.82842712474619010f : n == 16 ? 4.f : 5.65685424949238020f;
+    const float rn = 1.f / (float)n;  // exact (n is a power of two)
+    const int my[2] = {my_nx[0], my_nx[1]}, mx[2] = {mx_nx[0], mx_nx[1]};
+    const bool mv[2] = {mv_nx[0], mv_nx[1]};
     // members 0..n-1 all present (the normal case)?
     const uint32_t vm = (uint32_t)(__ballot(mv[0]) & 0xffffu) | ((uint32_t)(__ballot(mv[1]) & 0xffffu) << 16);
     const bool all_present = vm == (n == 32 ? ~0u : (1u << n) - 1u);
@@ -803,11 +826,16 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
         f32x4 a[4];
+        if (STEP == 1) {
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++) {
-          const float* src = src0 + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+          for (int kt = 0; kt < 4; kt++) a[kt] = an[gt][kt];
+        } else {
 #pragma unroll
-          for (int v = 0; v < 4; v++) a[kt][v] = ldg(src + v);  // always a valid pixel
+          for (int kt = 0; kt < 4; kt++) {
+            const float* src = src0 + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+#pragma unroll
+            for (int v = 0; v < 4; v++) a[kt][v] = ldg(src + v);  // always a valid pixel
+          }
         }
         if (!all_present) {  // an absent member enters as a zero patch
 #pragma unroll
@@ -922,6 +950,11 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
                                   : XF::mma(XF::cvt(D2[0][ct]), Hf[gt][0], zero4());
         D3[ct][gt] = acc * (rn * wm[gt]);
       }
+    }
+    // the next reference's positions and noisy pixels, then slots two ahead
+    if (j + 1 < nrefs) {
+      stage();
+      if (j + 2 < nrefs) prefetch(j + 2);
     }
     // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
 #pragma unroll
