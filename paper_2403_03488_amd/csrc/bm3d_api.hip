@@ -321,10 +321,11 @@ struct bm3d_batch {
   std::vector<bm3d_image_desc> imgs;
   std::vector<ImgDesc> hd;
   ImgDesc* dd = nullptr;
-  int* dprefix[LIST_KINDS] = {nullptr, nullptr, nullptr, nullptr};
+  int* dprefix[LIST_KINDS] = {};
   std::vector<int> hprefix[LIST_KINDS];
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  int* ctr = nullptr;  // dynamic filter-tile counter pair (zero between launches)
   int cus = 256;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -356,7 +357,9 @@ void fill_prefix(const ImgDesc* d, int n, const KParams& kp, std::vector<int>* p
 int batch_stage(bm3d_batch* b, int stage, int i0, int i1, hipStream_t s) {
   const int L = list_of_stage(stage);
   BatchRef br{b->dd, b->dprefix[L], b->n, b->hprefix[L][i0], b->hprefix[L][i1]};
-  int r = launch_batch(stage, b->p.xform, br, b->kp, persistent_blocks(b->p, b->cus), s, want_sync(&b->p));
+  if (stage == STAGE_FILTER1 || stage == STAGE_FILTER2) br.ctr = b->ctr;
+  int r = launch_batch(stage, b->p.xform, br, b->kp, persistent_blocks(b->p, b->cus), s, want_sync(&b->p),
+                       b->cus);
   return r == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
 
@@ -396,7 +399,7 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
   fill_prefix(b->hd.data(), n, b->kp, b->hprefix);
   const size_t desc_bytes = align_up(sizeof(ImgDesc) * n);
   const size_t pre_bytes = align_up(sizeof(int) * (n + 1));
-  const size_t all = tot + desc_bytes + LIST_KINDS * pre_bytes;
+  const size_t all = tot + desc_bytes + LIST_KINDS * pre_bytes + 256;
   if (hipMalloc((void**)&b->ws, all) != hipSuccess) {
     delete b;
     return BM3D_ERR_NOMEM;
@@ -405,7 +408,9 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
   for (int i = 0; i < n; i++) bind_workspace(b->hd[i], b->ws + base[i], Ls[i]);
   b->dd = (ImgDesc*)(b->ws + tot);
   for (int L = 0; L < LIST_KINDS; L++) b->dprefix[L] = (int*)(b->ws + tot + desc_bytes + L * pre_bytes);
+  b->ctr = (int*)(b->ws + tot + desc_bytes + LIST_KINDS * pre_bytes);
   bool ok = hipMemcpy(b->dd, b->hd.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemset(b->ctr, 0, 2 * sizeof(int)) == hipSuccess;
   for (int L = 0; L < LIST_KINDS && ok; L++)
     ok = hipMemcpy(b->dprefix[L], b->hprefix[L].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) ==
          hipSuccess;
@@ -530,7 +535,8 @@ extern "C" int bm3d_server_create(int max_requests, const bm3d_params* p, bm3d_s
   s->table_bytes = 7 * group_bytes(max_requests);
   for (int k = 0; k < 2; k++) {
     if (hipHostMalloc((void**)&s->host[k], s->table_bytes, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&s->dev[k], s->table_bytes) != hipSuccess ||
+        hipMalloc((void**)&s->dev[k], s->table_bytes + 256) != hipSuccess ||
+        hipMemset(s->dev[k] + s->table_bytes, 0, 2 * sizeof(int)) != hipSuccess ||
         hipEventCreateWithFlags(&s->done[k], hipEventDisableTiming) != hipSuccess) {
       bm3d_server_destroy(s);
       return BM3D_ERR_NOMEM;
@@ -596,7 +602,8 @@ extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
     const int* hpre = (const int*)(hb + off[stg] + align_up(sizeof(ImgDesc) * m));
     const int* hfill = (const int*)((const char*)hpre + align_up(sizeof(int) * (m + 1)));
     BatchRef br{dd, pre, m, 0, hpre[m]};
-    if (launch_batch(stg, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;
+    if (stg == STAGE_FILTER1 || stg == STAGE_FILTER2) br.ctr = (int*)(s->dev[k] + s->table_bytes);
+    if (launch_batch(stg, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p), s->cus)) return BM3D_ERR_HIP;
     if (stg == STAGE_PREP || stg == STAGE_AGG1) {
       BatchRef bf{dd, pfill, m, 0, hfill[m]};
       if (launch_batch(STAGE_FILL, s->p.xform, bf, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;

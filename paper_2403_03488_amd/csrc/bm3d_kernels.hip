@@ -1077,13 +1077,31 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   // would be re-read after every store the compiler cannot disambiguate)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
-  for (int i = br.begin + blockIdx.x * C::kWaves + wave; i < br.end; i += gridDim.x * C::kWaves) {
+  // With a counter, tiles go to waves as they become free (tile costs vary
+  // with group sizes and image edges, and a workgroup holds its LDS until
+  // its last wave ends); one atomic per tile, against the tile's ~10^5
+  // cycles, all lanes taking part with lane 0 adding 1.  Without one, wave w
+  // of workgroup b takes every (gridDim.x * kWaves)-th tile from
+  // b * kWaves + w.
+  const int l = lane_id();
+  const bool dyn = br.ctr != nullptr;
+  const int total = br.end - br.begin, stride = gridDim.x * C::kWaves;
+  int t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : blockIdx.x * C::kWaves + wave);
+  while (t < total) {
+    const int i = br.begin + t;
     const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
     const ImgDesc d = ldc(br.ds + im);
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
     filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wnum);
+    t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : t + stride);
+  }
+  // every wave has drawn an index past the end; the last one to get here
+  // zeroes the pair for the next launch
+  if (dyn && l == 0 && atomicAdd(br.ctr + 1, 1) == (int)gridDim.x * C::kWaves - 1) {
+    atomicExch(br.ctr, 0);
+    atomicExch(br.ctr + 1, 0);
   }
 }
 
@@ -1220,7 +1238,7 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
 }
 
 int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, int blocks, hipStream_t s,
-                 bool sync) {
+                 bool sync, int cus) {
   // blocks = 0: one workgroup per item (per filter_waves() items for the
   // filters); otherwise a persistent grid of that many workgroups.
   const int nw = br.end - br.begin;
@@ -1250,8 +1268,11 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
       const int wv = filter_waves(xform);
-      int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
       size_t b = filter_lds_bytes(xform, S, kp.tile);
+      int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
+      // dynamic tiles: as many workgroups as fit on the device at once
+      if (br.ctr && cus > 0)
+        g = std::min((nw + wv - 1) / wv, cus * std::max(1, (int)(163840 / b)));
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
     lds_attr(kb_filter<STEP, XF>, b);                                                     \

@@ -51,11 +51,16 @@ struct BatchRef {
   const int* prefix;   // device prefix item counts for the stage's list kind (nimg+1)
   int nimg;
   int begin, end;      // item range of this launch
+  // optional device pair {next item, finished waves}, zero before a launch:
+  // the filter stages then hand out tiles to waves dynamically, and the
+  // last wave to finish zeroes the pair again (launches using one pair must
+  // not overlap)
+  int* ctr = nullptr;
 };
 
 int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s, bool sync);
 int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, int blocks, hipStream_t s,
-                 bool sync);
+                 bool sync, int cus = 0);
 size_t stage_lds_bytes(int stage, int xform, const KParams& kp);
 int elem_chunk();
 int filter_block_waves(int xform);
