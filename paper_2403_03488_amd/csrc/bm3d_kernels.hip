@@ -335,11 +335,12 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 
 #pragma unroll
   for (int pass = 0; pass < kM1Passes; pass++) {
-    // this pass: reference columns v = 2*pass, 2*pass+1; local reference
-    // index lr = 2q + (v - 2*pass), key slot lr*RS + widx
-    int slot[2];
+    // this pass: reference columns v = CP*pass .. CP*pass + CP-1; local
+    // reference index lr = CP*q + (v - CP*pass), key slot lr*RS + widx
+    constexpr int CP = 4 / kM1Passes;
+    int slot[CP];
 #pragma unroll
-    for (int i = 0; i < 2; i++) slot[i] = (2 * q + i) * RS + wofs[2 * pass + i];
+    for (int i = 0; i < CP; i++) slot[i] = (CP * q + i) * RS + wofs[CP * pass + i];
     // each wave takes whole candidate rows cy (every nwaves-th), all 16-column
     // blocks of a row at once (at most 3: the union window is <= 48 wide)
     for (int cy = wv; cy < g.ny; cy += nwaves) {
@@ -370,8 +371,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
         const int cx = 16 * j + col;
         const int t = cy * SW + cx;
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-          const int v = 2 * pass + i;
+        for (int i = 0; i < CP; i++) {
+          const int v = CP * pass + i;
           // the distance alone; the key is formed when the slot is read back
           if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
             keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc[j] - 2 * Dm[j][v]);
@@ -381,7 +382,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     __syncthreads();
     // a reference is not its own candidate
     if (tid < kM1PassRefs) {
-      const int a = tid >> 1, b = 2 * pass + (tid & 1);
+      const int a = tid / CP, b = CP * pass + tid % CP;
       if (a < g.nri && b < g.nci) {
         int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
         window_1d(ry, h, S, wy, t0);
@@ -391,16 +392,18 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     }
     __syncthreads();
 
-    // each wave selects the groups of local references wave and wave + 4
-    static_assert(kM1PassRefs == 8, "two references per wave with four waves");
-    {
+    // each wave selects the groups of local references wave + 4r + 8rd
+    // (two at a time, side by side)
+    static_assert(kM1PassRefs % 8 == 0, "two references per wave and round with four waves");
+#pragma unroll 1
+    for (int rd = 0; rd < kM1PassRefs / 8; rd++) {
       uint32_t k[2][16];
       bool act[2];
       uint32_t* buf[2];
 #pragma unroll
       for (int r = 0; r < 2; r++) {
-        const int m = wave + 4 * r;
-        const int a = m >> 1, b = 2 * pass + (m & 1);
+        const int m = wave + 4 * r + 8 * rd;
+        const int a = m / CP, b = CP * pass + m % CP;
         act[r] = m < kM1PassRefs && a < g.nri && b < g.nci;
         buf[r] = keys + (act[r] ? m : 0) * RS;
         // key = distance << 10 | window index for candidates within the
@@ -418,8 +421,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
       for (int r = 0; r < 2; r++) {
         if (!act[r]) continue;
-        const int m = wave + 4 * r;
-        const int a = m >> 1, b = 2 * pass + (m & 1);
+        const int m = wave + 4 * r + 8 * rd;
+        const int a = m / CP, b = CP * pass + m % CP;
         int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
         window_1d(ry, h, S, wy, t0);
         window_1d(rx, w, S, wx, t0);
