@@ -148,6 +148,34 @@ int bm3d_luminance(const float* basic, int h, int w, int c, float* lum, bm3d_str
 int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_params* params,
                  float* out, bm3d_stream_t stream);
 
+/* ---- NL-means: the paper's alternative non-local first stage ----
+ * The NLM-G column of Table 3 and the "Ours-FL (NLM)" results (Section III)
+ * use NL-means in place of BM3D; the paper cites the pixelwise NL-means of
+ * Buades, Coll and Morel, which this computes: for every pixel p,
+ *   u_hat(p) = sum_q w(p,q) u(q) / sum_q w(p,q) over the (2r+1)^2 search
+ *   window of p clipped to the image, with
+ *   w(p,q) = exp(-max(d2(p,q) - 2 sigma^2, 0) / h^2) for q != p, d2 the mean
+ *   squared difference of the (2f+1)^2 patches over pixels and channels
+ *   (patch pixels outside the image read from its symmetric extension), and
+ *   w(p,p) = the largest w(p,q), q != p.
+ * Colour images are compared and averaged in RGB (no opponent transform). */
+typedef struct {
+  int patch_radius;  /* f: patches are (2f+1)^2, 0..8 */
+  int search_radius; /* r: windows are (2r+1)^2, 1..24 */
+  float h;           /* filtering parameter, > 0 */
+} bm3d_nlm_params;
+
+/* The published sigma table (grey: f = 1..5, r = 10 or 17, h = 0.40..0.30
+ * sigma; colour: f = 1..3, h = 0.55..0.35 sigma).  sigma > 0, c = 1 or 3. */
+int bm3d_nlm_params_default(float sigma, int c, bm3d_nlm_params* p);
+
+/* NL-means of one image.  img: device HWC uint8 [h][w][c]; out: device HWC
+ * float [h][w][c] on the [0,255] scale, unclipped.  Allocates nothing; the
+ * arguments are validated on the host (BM3D_ERR_ARG) before anything is
+ * enqueued on `stream`. */
+int bm3d_nlm(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_nlm_params* p,
+             float* out, bm3d_stream_t stream);
+
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
  * image's working buffers and a device table of image descriptors with

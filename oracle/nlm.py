@@ -50,30 +50,37 @@ def _planes(img):
     return np.moveaxis(a, 2, 0), a.shape[2]
 
 
+def _offsets(r):
+    return [(dy, dx) for dy in range(-r, r + 1) for dx in range(-r, r + 1) if (dy, dx) != (0, 0)]
+
+
+def _exponent(u, pad, g, sigma, f, dy, dx):
+    """max(d2(p, p + o) - 2 sigma^2, 0) for every pixel p, +inf where p + o
+    lies outside the image (o = (dy, dx))."""
+    C, H, W = u.shape
+    d2 = np.zeros((H, W))
+    for ky in range(-f, f + 1):
+        for kx in range(-f, f + 1):
+            a = pad[:, g + ky:g + ky + H, g + kx:g + kx + W]
+            b = pad[:, g + dy + ky:g + dy + ky + H, g + dx + kx:g + dx + kx + W]
+            d2 += ((a - b) ** 2).sum(axis=0)
+    d2 /= C * (2 * f + 1) ** 2
+    e = np.maximum(d2 - 2.0 * sigma * sigma, 0.0)
+    yy, xx = np.mgrid[0:H, 0:W]
+    inside = (yy + dy >= 0) & (yy + dy < H) & (xx + dx >= 0) & (xx + dx < W)
+    return np.where(inside, e, np.inf)
+
+
 def exponents(img, sigma: float, f: int, r: int):
     """E[o, y, x] = max(d2(p, p + o) - 2 sigma^2, 0) for every search offset o
     = (dy, dx) in [-r, r]^2 except (0, 0), row-major; +inf where p + o lies
-    outside the image.  Also returns the offsets."""
-    u, C = _planes(img)
-    _, H, W = u.shape
+    outside the image.  Also returns the offsets.  (Small images only: it
+    holds every offset at once.)"""
+    u, _ = _planes(img)
     g = f + r
     pad = np.pad(u, ((0, 0), (g, g), (g, g)), mode="symmetric")
-    yy, xx = np.mgrid[0:H, 0:W]
-    offs = [(dy, dx) for dy in range(-r, r + 1) for dx in range(-r, r + 1) if (dy, dx) != (0, 0)]
-    E = np.empty((len(offs), H, W))
-    P = (2 * f + 1) ** 2
-    for i, (dy, dx) in enumerate(offs):
-        d2 = np.zeros((H, W))
-        for ky in range(-f, f + 1):
-            for kx in range(-f, f + 1):
-                a = pad[:, g + ky:g + ky + H, g + kx:g + kx + W]
-                b = pad[:, g + dy + ky:g + dy + ky + H, g + dx + kx:g + dx + kx + W]
-                d2 += ((a - b) ** 2).sum(axis=0)
-        d2 /= C * P
-        e = np.maximum(d2 - 2.0 * sigma * sigma, 0.0)
-        inside = (yy + dy >= 0) & (yy + dy < H) & (xx + dx >= 0) & (xx + dx < W)
-        E[i] = np.where(inside, e, np.inf)
-    return E, offs
+    offs = _offsets(r)
+    return np.stack([_exponent(u, pad, g, sigma, f, dy, dx) for dy, dx in offs]), offs
 
 
 def nlm(img, sigma: float, f: int | None = None, r: int | None = None, h: float | None = None):
@@ -87,16 +94,20 @@ def nlm(img, sigma: float, f: int | None = None, r: int | None = None, h: float 
     h = dh if h is None else h
     if not h > 0:
         raise ValueError("h must be positive")
-    E, offs = exponents(img, sigma, f, r)
-    Emin = E.min(axis=0)  # +inf only where the window holds p alone
+    g = f + r
+    pad = np.pad(u, ((0, 0), (g, g), (g, g)), mode="symmetric")
+    offs = _offsets(r)
+    # first pass: the smallest exponent of each window (+inf only where the
+    # window holds p alone); second pass: the weights relative to it
+    Emin = np.full((H, W), np.inf)
+    for dy, dx in offs:
+        Emin = np.minimum(Emin, _exponent(u, pad, g, sigma, f, dy, dx))
     num = u.copy()        # the centre, weight exp(-(E_min - E_min)/h^2) = 1
     den = np.ones((H, W))
-    g = r
-    padu = np.pad(u, ((0, 0), (g, g), (g, g)), mode="symmetric")
-    for i, (dy, dx) in enumerate(offs):
-        w = np.exp(-(E[i] - Emin) / (h * h))  # 0 where p + o is outside
-        w = np.where(np.isfinite(E[i]), w, 0.0)
-        num += w * padu[:, g + dy:g + dy + H, g + dx:g + dx + W]
+    for dy, dx in offs:
+        E = _exponent(u, pad, g, sigma, f, dy, dx)
+        w = np.where(np.isfinite(E), np.exp(-(E - Emin) / (h * h)), 0.0)  # 0 outside
+        num += w * pad[:, g + dy:g + dy + H, g + dx:g + dx + W]
         den += w
     out = num / den
     return out[0] if C == 1 else np.moveaxis(out, 0, 2)

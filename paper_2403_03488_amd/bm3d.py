@@ -41,6 +41,10 @@ class Params(ctypes.Structure):
         return q
 
 
+class NlmParams(ctypes.Structure):
+    _fields_ = [("patch_radius", ctypes.c_int), ("search_radius", ctypes.c_int), ("h", ctypes.c_float)]
+
+
 class ImageDesc(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
                 ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
@@ -65,6 +69,8 @@ _SIGS = {
     "bm3d_aggregate": (_i, [_vp, _vp, _i, _i, _i, _i, _PP, _vp, _vp]),
     "bm3d_luminance": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "bm3d_denoise": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
+    "bm3d_nlm_params_default": (_i, [_f, _i, ctypes.POINTER(NlmParams)]),
+    "bm3d_nlm": (_i, [_vp, _i, _i, _i, _f, ctypes.POINTER(NlmParams), _vp, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -207,6 +213,26 @@ def denoise(img, sigma: float, p: Params | None = None, out=None, workspace=None
     _check(_lib.bm3d_denoise(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma),
                              ctypes.byref(p), _ptr(out, torch.float32, "out"), _stream(stream)),
            "bm3d_denoise")
+    return out
+
+
+def nlm_params_default(sigma: float, c: int = 1) -> NlmParams:
+    p = NlmParams()
+    _check(_lib.bm3d_nlm_params_default(float(sigma), int(c), ctypes.byref(p)), "bm3d_nlm_params_default")
+    return p
+
+
+def nlm(img, sigma: float, p: NlmParams | None = None, out=None, stream=None):
+    """NL-means of one device image (uint8 [h,w] or [h,w,3]).  Returns a
+    float32 device tensor of the same shape on the [0,255] scale."""
+    torch = _torch()
+    h, w = img.shape[0], img.shape[1]
+    c = 1 if img.dim() == 2 else img.shape[2]
+    p = p or nlm_params_default(sigma, c)
+    if out is None:
+        out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+    _check(_lib.bm3d_nlm(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma), ctypes.byref(p),
+                         _ptr(out, torch.float32, "out"), _stream(stream)), "bm3d_nlm")
     return out
 
 

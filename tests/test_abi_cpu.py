@@ -62,6 +62,29 @@ def test_defaults_and_geometry(B):
     assert B.strerror(0) == "ok" and "argument" in B.strerror(-1)
 
 
+def test_nlm_defaults_and_validation(B):
+    assert ctypes.sizeof(B.NlmParams) == 12
+    p = B.nlm_params_default(25.0, 1)
+    assert (p.patch_radius, p.search_radius) == (2, 10) and abs(p.h - 10.0) < 1e-5
+    q = B.nlm_params_default(50.0, 3)
+    assert (q.patch_radius, q.search_radius) == (2, 17) and abs(q.h - 20.0) < 1e-5
+    L = B._lib
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ref = ctypes.byref
+    assert L.bm3d_nlm_params_default(0.0, 1, ref(B.NlmParams())) == -1
+    assert L.bm3d_nlm_params_default(25.0, 2, ref(B.NlmParams())) == -1
+    assert L.bm3d_nlm(None, 64, 64, 1, 25.0, ref(p), fake, None) == -1
+    assert L.bm3d_nlm(fake, 0, 64, 1, 25.0, ref(p), fake, None) == -1
+    assert L.bm3d_nlm(fake, 64, 64, 2, 25.0, ref(p), fake, None) == -1
+    assert L.bm3d_nlm(fake, 64, 64, 1, float("nan"), ref(p), fake, None) == -1
+    assert L.bm3d_nlm(fake, 64, 64, 1, 25.0, None, fake, None) == -1
+    for field, val in (("patch_radius", -1), ("patch_radius", 9), ("search_radius", 0),
+                       ("search_radius", 25), ("h", 0.0), ("h", float("inf"))):
+        bad = B.NlmParams(p.patch_radius, p.search_radius, p.h)
+        setattr(bad, field, val)
+        assert L.bm3d_nlm(fake, 64, 64, 1, 25.0, ref(bad), fake, None) == -1, field
+
+
 def test_host_validation_rejects_before_enqueue(B):
     L = B._lib
     p = B.params_default(25.0)

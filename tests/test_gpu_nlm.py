@@ -1,0 +1,78 @@
+"""NL-means through the C ABI against the FP64 oracle, pixel by pixel.
+
+The kernel computes in FP32 the same sum as the oracle (weights relative to
+the window's smallest exponent); the bar is max |difference| <= 1e-3 on the
+[0, 255] scale, as for the FP32 BM3D form: a patch distance is a sum of at
+most 363 squared differences (relative rounding ~2e-5), and a weight's
+relative error is that distance error over h^2."""
+import numpy as np
+import pytest
+
+from oracle import nlm as O
+from paper_2403_03488_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_03488_amd import bm3d
+    return bm3d
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def run(B, img, sigma, params=None):
+    c = 1 if img.ndim == 2 else img.shape[2]
+    p = B.nlm_params_default(sigma, c)
+    if params:
+        p = B.NlmParams(*params)
+    out = B.nlm(torch.from_numpy(np.ascontiguousarray(img)).cuda(), sigma, p)
+    torch.cuda.synchronize()
+    ref = O.nlm(img, sigma, f=p.patch_radius, r=p.search_radius, h=p.h)
+    got = out.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref)
+    log("nlm %s sigma %.0f f=%d r=%d h=%.2f: max|diff| %.2e mean %.2e" %
+        (img.shape, sigma, p.patch_radius, p.search_radius, p.h, err.max(), err.mean()))
+    return err, got, ref
+
+
+@pytest.mark.parametrize("which", ["small_gray", "gray512", "colour"])
+def test_nlm_matches_oracle(B, which):
+    s = {"small_gray": synth.small_gray, "gray512": synth.gray_512, "colour": synth.colour_481x321}[which]()
+    err, got, _ = run(B, s.noisy, s.sigma)
+    assert err.max() <= TOL
+    # it denoises: the estimate is closer to the clean image than the input
+    assert synth.psnr(s.clean, got) > synth.psnr(s.clean, s.noisy.astype(np.float64)) + 5
+
+
+def test_nlm_high_sigma_wide_window(B):
+    # sigma = 50 grey: 9 x 9 patches, 35 x 35 windows
+    s = synth.gray_512(sigma=50.0)
+    err, _, _ = run(B, s.noisy[100:196, 200:280], 50.0)
+    assert err.max() <= TOL
+
+
+@pytest.mark.parametrize("shape", [(9, 13), (3, 40), (6, 7, 3), (70, 1)])
+def test_nlm_small_and_thin(B, shape):
+    # windows and patches larger than the image: clipping and the symmetric extension
+    rng = np.random.default_rng(sum(shape))
+    img = rng.integers(0, 256, shape).astype(np.uint8)
+    err, _, _ = run(B, img, 25.0)
+    assert err.max() <= TOL
+
+
+def test_nlm_constant_and_explicit_params(B):
+    img = np.full((40, 90), 77, np.uint8)
+    err, got, _ = run(B, img, 25.0)
+    assert np.array_equal(got, img.astype(np.float64))
+    rng = np.random.default_rng(2)
+    img = rng.integers(0, 256, (50, 70, 3)).astype(np.uint8)
+    err, _, _ = run(B, img, 20.0, params=(0, 5, 7.5))  # 1 x 1 patches
+    assert err.max() <= TOL
