@@ -176,6 +176,13 @@ int bm3d_nlm_params_default(float sigma, int c, bm3d_nlm_params* p);
 int bm3d_nlm(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_nlm_params* p,
              float* out, bm3d_stream_t stream);
 
+/* NL-means of n (1..64) images of one size, channel count and sigma in a
+ * single launch.  imgs[i] / outs[i]: device pointers as in bm3d_nlm; the two
+ * arrays themselves are host memory, read before the call returns.
+ * Allocates nothing. */
+int bm3d_nlm_batch(const uint8_t* const* imgs, float* const* outs, int n, int h, int w, int c,
+                   float sigma, const bm3d_nlm_params* p, bm3d_stream_t stream);
+
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
  * image's working buffers and a device table of image descriptors with

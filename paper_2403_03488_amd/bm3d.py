@@ -71,6 +71,8 @@ _SIGS = {
     "bm3d_denoise": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
     "bm3d_nlm_params_default": (_i, [_f, _i, ctypes.POINTER(NlmParams)]),
     "bm3d_nlm": (_i, [_vp, _i, _i, _i, _f, ctypes.POINTER(NlmParams), _vp, _vp]),
+    "bm3d_nlm_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i, _i, _f,
+                            ctypes.POINTER(NlmParams), _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -234,6 +236,26 @@ def nlm(img, sigma: float, p: NlmParams | None = None, out=None, stream=None):
     _check(_lib.bm3d_nlm(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma), ctypes.byref(p),
                          _ptr(out, torch.float32, "out"), _stream(stream)), "bm3d_nlm")
     return out
+
+
+def nlm_batch(imgs, sigma: float, p: NlmParams | None = None, outs=None, stream=None):
+    """NL-means of up to 64 device images of one shape in one launch.
+    Returns the list of float32 outputs."""
+    torch = _torch()
+    n = len(imgs)
+    h, w = imgs[0].shape[0], imgs[0].shape[1]
+    c = 1 if imgs[0].dim() == 2 else imgs[0].shape[2]
+    p = p or nlm_params_default(sigma, c)
+    if outs is None:
+        outs = [torch.empty(imgs[0].shape, dtype=torch.float32, device=imgs[0].device) for _ in range(n)]
+    for t in imgs:
+        if tuple(t.shape) != tuple(imgs[0].shape):
+            raise ValueError("nlm_batch: images must share one shape")
+    ia = (_vp * n)(*[_ptr(t, torch.uint8, "img") for t in imgs])
+    oa = (_vp * n)(*[_ptr(t, torch.float32, "out") for t in outs])
+    _check(_lib.bm3d_nlm_batch(ia, oa, n, h, w, c, float(sigma), ctypes.byref(p), _stream(stream)),
+           "bm3d_nlm_batch")
+    return outs
 
 
 def autotune(p: Params, cache_path: str | None = None) -> Params:

@@ -11,14 +11,16 @@
 // i.e. weights exp(-E/h^2) with the centre weighted like its best match,
 // all scaled by exp(E_min/h^2) (a common factor) so nothing underflows.
 //
-// One 256-thread workgroup owns a 64 x 16 output tile and keeps the tile
-// plus a symmetric halo of r + f pixels in LDS.  Per search offset it forms
-// the squared-difference image over the tile and its patch halo, then the
-// horizontal and the vertical patch sums; each thread then updates its 4
-// pixels.  E_min is tracked on line: a candidate below the running minimum
-// rescales the sums instead of being rescaled, so each candidate costs one
-// exponential.  Every LDS address a thread touches for an offset is its
-// address for offset (0, 0) plus one uniform shift.
+// One wave (a 64-thread workgroup) owns a strip of kRows output rows and
+// 64 - 2f output columns, with the strip and a symmetric halo of r + f
+// pixels in LDS.  Lane l stands for image column x0 - f + l.  Per search
+// offset, for each of the kRows + 2f rows it forms the squared difference of
+// its column (its reference samples stay in registers), adds those of lanes
+// l + 1 .. l + 2f through cross-lane permutes (the horizontal patch sums, so
+// lanes 0 .. 63 - 2f hold outputs), sums 2f + 1 of those rows per output
+// row, and updates each output's sums with one exponential.  E_min is
+// tracked on line: a candidate below the running minimum rescales the sums
+// instead of being rescaled.  There is no barrier after the strip is loaded.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,34 +30,22 @@
 
 namespace nlm {
 
-constexpr int kTW = 64, kTH = 16, kThreads = 256;
+constexpr int kRows = 8;          // output rows per wave
+constexpr int kMaxBatch = 64;     // images of one batched launch (pointers in the kernel arguments)
+
+struct Batch {
+  const uint8_t* img[kMaxBatch];
+  float* out[kMaxBatch];
+};
 constexpr int kMaxF = 8, kMaxR = 24;
 constexpr size_t kLdsBudget = 160 * 1024;
-// per-thread element counts of the difference and horizontal-sum passes
-constexpr int kMaxDE = ((kTH + 2 * kMaxF) * (kTW + 2 * kMaxF) + kThreads - 1) / kThreads;
-constexpr int kMaxHE = ((kTH + 2 * kMaxF) * kTW + kThreads - 1) / kThreads;
 
-struct Geo {
-  int f, r, g;     // patch radius, search radius, halo = f + r
-  int RH, RP;      // region rows and row pitch (floats)
-  int DH, DW;      // difference image rows, columns (tile + patch halo)
-};
-
-__host__ __device__ inline Geo geo(int f, int r) {
-  Geo q;
-  q.f = f;
-  q.r = r;
-  q.g = f + r;
-  q.RH = kTH + 2 * q.g;
-  q.RP = kTW + 2 * q.g + 1;  // odd pitch: column neighbours in different banks
-  q.DH = kTH + 2 * f;
-  q.DW = kTW + 2 * f;
-  return q;
-}
-
+__host__ __device__ inline int out_cols(int f) { return 64 - 2 * f; }
+// strip rows and row pitch (floats) of the LDS region
+__host__ __device__ inline int region_rows(int f, int r) { return kRows + 2 * (f + r); }
+__host__ __device__ inline int region_pitch(int r) { return 64 + 2 * r + 1; }
 __host__ __device__ inline size_t lds_bytes(int c, int f, int r) {
-  const Geo q = geo(f, r);
-  return ((size_t)c * q.RH * q.RP + (size_t)q.DH * q.DW + (size_t)q.DH * kTW) * 4;
+  return (size_t)c * region_rows(f, r) * region_pitch(r) * 4;
 }
 
 // index into the symmetric extension of [0, n) (edge sample repeated)
@@ -66,110 +56,127 @@ __device__ inline int reflect(int t, int n) {
   return t < n ? t : p - 1 - t;
 }
 
-template <int C>
-__global__ void __launch_bounds__(kThreads) k_nlm(const uint8_t* __restrict__ img, int H, int W,
-                                                  float two_sig2, float k2, float inv_cp, int f, int r,
-                                                  float* __restrict__ out) {
-  extern __shared__ float sm[];
-  const Geo q = geo(f, r);
-  const int plane = q.RH * q.RP;
-  float* U = sm;                  // [C][RH][RP]  region (y0 - g + row, x0 - g + col)
-  float* D = U + C * plane;       // [DH][DW]     difference image (y0 - f + j, x0 - f + i)
-  float* Hs = D + q.DH * q.DW;    // [DH][kTW]    its horizontal patch sums
-  const int tid = threadIdx.x;
-  const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+__device__ inline float lane_down(float v, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
 
-  const int RW = kTW + 2 * q.g;
-  for (int i = tid; i < q.RH * RW; i += kThreads) {
+template <int C, int F>
+__global__ void __launch_bounds__(64) k_nlm(Batch bt, int H, int W, float two_sig2, float k2, float inv_cp,
+                                            int r) {
+  const uint8_t* __restrict__ img = bt.img[blockIdx.z];
+  float* __restrict__ out = bt.out[blockIdx.z];
+  constexpr int NR = kRows + 2 * F;  // difference rows of the strip
+  extern __shared__ float U[];       // [C][RH][RP]: image (y0 - f - r + i, x0 - f - r + j)
+  const int RH = region_rows(F, r), RP = region_pitch(r), RW = RP - 1;
+  const int plane = RH * RP;
+  const int l = threadIdx.x;
+  const int x0 = blockIdx.x * out_cols(F), y0 = blockIdx.y * kRows;
+  for (int i = l; i < RH * RW; i += 64) {
     const int yy = i / RW, xx = i - yy * RW;
-    const int gy = reflect(y0 - q.g + yy, H), gx = reflect(x0 - q.g + xx, W);
+    const int gy = reflect(y0 - F - r + yy, H), gx = reflect(x0 - F - r + xx, W);
     const uint8_t* s = img + ((size_t)gy * W + gx) * C;
 #pragma unroll
-    for (int c = 0; c < C; c++) U[c * plane + yy * q.RP + xx] = (float)s[c];
-  }
-
-  // this thread's elements of the two passes, as offset-(0, 0) addresses
-  int da[kMaxDE], ha[kMaxHE];
-  const int nde = q.DH * q.DW, nhe = q.DH * kTW;
-#pragma unroll
-  for (int k = 0; k < kMaxDE; k++) {
-    const int e = tid + k * kThreads;
-    const int j = e / q.DW, i = e - j * q.DW;
-    da[k] = (q.r + j) * q.RP + q.r + i;  // reference sample of D[e]
-  }
-#pragma unroll
-  for (int k = 0; k < kMaxHE; k++) {
-    const int e = tid + k * kThreads;
-    const int j = e / kTW, i = e - j * kTW;
-    ha[k] = j * q.DW + i;                // first D sample of Hs[e]
-  }
-  const int px = tid & 63, wv = tid >> 6;
-  const int X = x0 + px;
-  float num[C][4], den[4], mn[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    den[k] = 0.f;
-    mn[k] = __builtin_inff();
-#pragma unroll
-    for (int c = 0; c < C; c++) num[c][k] = 0.f;
+    for (int c = 0; c < C; c++) U[c * plane + yy * RP + xx] = (float)s[c];
   }
   __syncthreads();
 
-  const int taps = 2 * f + 1;
+  // lane l's column x0 - f + l is region column r + l; difference row rr is
+  // image row y0 - f + rr, region row r + rr
+  float ref[C][NR];
+#pragma unroll
+  for (int c = 0; c < C; c++)
+#pragma unroll
+    for (int rr = 0; rr < NR; rr++) ref[c][rr] = U[c * plane + (r + rr) * RP + r + l];
+  int addr[2 * F + 1];
+#pragma unroll
+  for (int t = 1; t <= 2 * F; t++) addr[t] = ((l + t) & 63) << 2;
+  const int X = x0 + l;                       // output column of lane l
+  const bool lane_out = l < out_cols(F) && X < W;
+  float num[C][kRows], den[kRows], mn[kRows];
+#pragma unroll
+  for (int o = 0; o < kRows; o++) {
+    den[o] = 0.f;
+    mn[o] = __builtin_inff();
+#pragma unroll
+    for (int c = 0; c < C; c++) num[c][o] = 0.f;
+  }
+
   for (int dy = -r; dy <= r; dy++) {
     for (int dx = -r; dx <= r; dx++) {
       if (dy == 0 && dx == 0) continue;
-      const int sh = dy * q.RP + dx;
+      const int cand = (r + dy) * RP + r + l + dx;  // candidate of difference row 0
+      float hs[NR];
 #pragma unroll
-      for (int k = 0; k < kMaxDE; k++) {
-        if (tid + k * kThreads >= nde) break;
-        float s = 0.f;
+      for (int rr = 0; rr < NR; rr++) {
+        float d = 0.f;
 #pragma unroll
         for (int c = 0; c < C; c++) {
-          const float e = U[c * plane + da[k]] - U[c * plane + da[k] + sh];
-          s = __builtin_fmaf(e, e, s);
+          const float e = ref[c][rr] - U[c * plane + cand + rr * RP];
+          d = __builtin_fmaf(e, e, d);
         }
-        D[tid + k * kThreads] = s;
-      }
-      __syncthreads();
+        float hsum = d;
 #pragma unroll
-      for (int k = 0; k < kMaxHE; k++) {
-        if (tid + k * kThreads >= nhe) break;
-        float s = 0.f;
-        for (int t = 0; t < taps; t++) s += D[ha[k] + t];
-        Hs[tid + k * kThreads] = s;
+        for (int t = 1; t <= 2 * F; t++) hsum += lane_down(d, addr[t]);
+        hs[rr] = hsum;
       }
-      __syncthreads();
-      const bool colok = X < W && X + dx >= 0 && X + dx < W;
+      const bool colok = lane_out && X + dx >= 0 && X + dx < W;
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const int yl = 4 * wv + k, Y = y0 + yl;
+      for (int o = 0; o < kRows; o++) {
+        const int Y = y0 + o;
         if (!(colok && Y < H && Y + dy >= 0 && Y + dy < H)) continue;
-        float d2 = 0.f;
-        for (int t = 0; t < taps; t++) d2 += Hs[(yl + t) * kTW + px];
+        float d2 = hs[o];
+#pragma unroll
+        for (int t = 1; t <= 2 * F; t++) d2 += hs[o + t];
         const float E = fmaxf(__builtin_fmaf(d2, inv_cp, -two_sig2), 0.f);
         // one exponential: the candidate below the running minimum rescales
         // the sums and takes weight 1, otherwise it takes the weight
-        const float diff = E - mn[k];
+        const float diff = E - mn[o];
         const float t = exp2f(-fabsf(diff) * k2);
         const bool lt = diff < 0.f;
-        const float s = lt ? t : 1.f, wq = lt ? 1.f : t;
-        const int ca = (q.g + yl + dy) * q.RP + q.g + px + dx;
+        const float sc = lt ? t : 1.f, wq = lt ? 1.f : t;
+        // the candidate pixel: region row f + r + o + dy, column f + r + l + dx
+        const int ca = (F + r + o + dy) * RP + F + r + l + dx;
 #pragma unroll
-        for (int c = 0; c < C; c++) num[c][k] = __builtin_fmaf(wq, U[c * plane + ca], num[c][k] * s);
-        den[k] = __builtin_fmaf(den[k], s, wq);
-        mn[k] = fminf(mn[k], E);
+        for (int c = 0; c < C; c++) num[c][o] = __builtin_fmaf(wq, U[c * plane + ca], num[c][o] * sc);
+        den[o] = __builtin_fmaf(den[o], sc, wq);
+        mn[o] = fminf(mn[o], E);
       }
     }
   }
 #pragma unroll
-  for (int k = 0; k < 4; k++) {
-    const int yl = 4 * wv + k, Y = y0 + yl;
-    if (Y >= H || X >= W) continue;
-    const int ca = (q.g + yl) * q.RP + q.g + px;
-    const float dn = 1.f + den[k];  // a division, not a reciprocal: flat areas come back exactly
+  for (int o = 0; o < kRows; o++) {
+    const int Y = y0 + o;
+    if (!lane_out || Y >= H) continue;
+    const int ca = (F + r + o) * RP + F + r + l;
+    const float dn = 1.f + den[o];  // a division, not a reciprocal: flat areas come back exactly
 #pragma unroll
-    for (int c = 0; c < C; c++) out[((size_t)Y * W + X) * C + c] = (U[c * plane + ca] + num[c][k]) / dn;
+    for (int c = 0; c < C; c++) out[((size_t)Y * W + X) * C + c] = (U[c * plane + ca] + num[c][o]) / dn;
+  }
+}
+
+template <int C, int F>
+int launch_nlm(const Batch& bt, int n, int h, int w, float two_sig2, float k2, float inv_cp, int r, hipStream_t s) {
+  const size_t lds = lds_bytes(C, F, r);
+  (void)hipFuncSetAttribute((const void*)k_nlm<C, F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  dim3 grid((w + out_cols(F) - 1) / out_cols(F), (h + kRows - 1) / kRows, n);
+  hipLaunchKernelGGL((k_nlm<C, F>), grid, dim3(64), lds, s, bt, h, w, two_sig2, k2, inv_cp, r);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int C>
+int launch_nlm_f(int f, const Batch& bt, int h, int w, float two_sig2, float k2, float inv_cp, int r, int n,
+                 hipStream_t s) {
+  switch (f) {
+    case 0: return launch_nlm<C, 0>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 1: return launch_nlm<C, 1>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 2: return launch_nlm<C, 2>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 3: return launch_nlm<C, 3>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 4: return launch_nlm<C, 4>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 5: return launch_nlm<C, 5>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 6: return launch_nlm<C, 6>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 7: return launch_nlm<C, 7>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    case 8: return launch_nlm<C, 8>(bt, n, h, w, two_sig2, k2, inv_cp, r, s);
+    default: return -1;
   }
 }
 
@@ -195,26 +202,50 @@ extern "C" int bm3d_nlm_params_default(float sigma, int c, bm3d_nlm_params* p) {
   return BM3D_ERR_ARG;
 }
 
-extern "C" int bm3d_nlm(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_nlm_params* p,
-                        float* out, bm3d_stream_t stream) {
-  if (!img || !out || !p || h < 1 || w < 1 || (c != 1 && c != 3)) return BM3D_ERR_ARG;
+// validates everything but the image pointers; 0 or a bm3d_status
+static int check_nlm(int h, int w, int c, float sigma, const bm3d_nlm_params* p) {
+  if (!p || h < 1 || w < 1 || (c != 1 && c != 3)) return BM3D_ERR_ARG;
   if ((long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
   if (!(sigma >= 0.f) || !std::isfinite(sigma)) return BM3D_ERR_ARG;
   const int f = p->patch_radius, r = p->search_radius;
   if (f < 0 || f > kMaxF || r < 1 || r > kMaxR || !(p->h > 0.f) || !std::isfinite(p->h)) return BM3D_ERR_ARG;
-  const size_t lds = lds_bytes(c, f, r);
-  if (lds > kLdsBudget) return BM3D_ERR_UNSUPPORTED;
+  if (lds_bytes(c, f, r) > kLdsBudget) return BM3D_ERR_UNSUPPORTED;
+  return BM3D_OK;
+}
+
+static int run_nlm(const Batch& bt, int n, int h, int w, int c, float sigma, const bm3d_nlm_params* p,
+                   bm3d_stream_t stream) {
+  const int f = p->patch_radius, r = p->search_radius;
   const float two_sig2 = 2.f * sigma * sigma;
   const float k2 = 1.4426950408889634f / (p->h * p->h);  // log2(e) / h^2
   const float inv_cp = 1.f / (float)(c * (2 * f + 1) * (2 * f + 1));
-  dim3 grid((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
   hipStream_t s = (hipStream_t)stream;
-  if (c == 1) {
-    (void)hipFuncSetAttribute((const void*)k_nlm<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_nlm<1>, grid, dim3(kThreads), lds, s, img, h, w, two_sig2, k2, inv_cp, f, r, out);
-  } else {
-    (void)hipFuncSetAttribute((const void*)k_nlm<3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_nlm<3>, grid, dim3(kThreads), lds, s, img, h, w, two_sig2, k2, inv_cp, f, r, out);
+  const int e = c == 1 ? launch_nlm_f<1>(f, bt, h, w, two_sig2, k2, inv_cp, r, n, s)
+                       : launch_nlm_f<3>(f, bt, h, w, two_sig2, k2, inv_cp, r, n, s);
+  return e == 0 ? BM3D_OK : BM3D_ERR_HIP;
+}
+
+extern "C" int bm3d_nlm(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_nlm_params* p,
+                        float* out, bm3d_stream_t stream) {
+  if (!img || !out) return BM3D_ERR_ARG;
+  const int e = check_nlm(h, w, c, sigma, p);
+  if (e) return e;
+  Batch bt{};
+  bt.img[0] = img;
+  bt.out[0] = out;
+  return run_nlm(bt, 1, h, w, c, sigma, p, stream);
+}
+
+extern "C" int bm3d_nlm_batch(const uint8_t* const* imgs, float* const* outs, int n, int h, int w, int c,
+                              float sigma, const bm3d_nlm_params* p, bm3d_stream_t stream) {
+  if (!imgs || !outs || n < 1 || n > kMaxBatch) return BM3D_ERR_ARG;
+  Batch bt{};
+  for (int i = 0; i < n; i++) {
+    if (!imgs[i] || !outs[i]) return BM3D_ERR_ARG;
+    bt.img[i] = imgs[i];
+    bt.out[i] = outs[i];
   }
-  return hipGetLastError() == hipSuccess ? BM3D_OK : BM3D_ERR_HIP;
+  const int e = check_nlm(h, w, c, sigma, p);
+  if (e) return e;
+  return run_nlm(bt, n, h, w, c, sigma, p, stream);
 }

@@ -78,6 +78,13 @@ def test_nlm_defaults_and_validation(B):
     assert L.bm3d_nlm(fake, 64, 64, 2, 25.0, ref(p), fake, None) == -1
     assert L.bm3d_nlm(fake, 64, 64, 1, float("nan"), ref(p), fake, None) == -1
     assert L.bm3d_nlm(fake, 64, 64, 1, 25.0, None, fake, None) == -1
+    arr = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    assert L.bm3d_nlm_batch(arr, arr, 0, 64, 64, 1, 25.0, ref(p), None) == -1
+    assert L.bm3d_nlm_batch(arr, arr, 65, 64, 64, 1, 25.0, ref(p), None) == -1
+    assert L.bm3d_nlm_batch(None, arr, 2, 64, 64, 1, 25.0, ref(p), None) == -1
+    holes = (ctypes.c_void_p * 2)(0x1000, None)
+    assert L.bm3d_nlm_batch(arr, holes, 2, 64, 64, 1, 25.0, ref(p), None) == -1
+    assert L.bm3d_nlm_batch(arr, arr, 2, 64, 64, 2, 25.0, ref(p), None) == -1
     for field, val in (("patch_radius", -1), ("patch_radius", 9), ("search_radius", 0),
                        ("search_radius", 25), ("h", 0.0), ("h", float("inf"))):
         bad = B.NlmParams(p.patch_radius, p.search_radius, p.h)

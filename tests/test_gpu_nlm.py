@@ -76,3 +76,17 @@ def test_nlm_constant_and_explicit_params(B):
     img = rng.integers(0, 256, (50, 70, 3)).astype(np.uint8)
     err, _, _ = run(B, img, 20.0, params=(0, 5, 7.5))  # 1 x 1 patches
     assert err.max() <= TOL
+
+
+def test_nlm_batch_equals_single(B):
+    # one launch over several images gives each image's single-image result
+    imgs = [synth.small_gray(index=i).noisy for i in range(5)]
+    dev = [torch.from_numpy(x).cuda() for x in imgs]
+    outs = B.nlm_batch(dev, 25.0)
+    for x, o in zip(dev, outs):
+        single = B.nlm(x, 25.0)
+        torch.cuda.synchronize()
+        assert torch.equal(o, single)
+    err = np.abs(outs[3].cpu().numpy().astype(np.float64) - O.nlm(imgs[3], 25.0)).max()
+    log("nlm batch image 3: max|diff| %.2e" % err)
+    assert err <= TOL
