@@ -30,6 +30,8 @@ PEAK = {  # MI355X published dense peaks
     "bf16": 2.5e15, "fp16": 2.5e15, "fp32_mfma": 157.3e12, "int8": 5.0e15,
     # vector FP32 without packed instructions: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
     "fp32_valu": 78.6e12,
+    # vector lane operations: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+    "valu_ops": 39.3e12,
 }
 XF = {"fp32": 0, "bf16": 1, "fp16": 2}
 
@@ -138,6 +140,81 @@ def tuned_params(args, bm3d, sigma, flags=0):
     if args.persistent >= 0:
         p.persistent_wgs = args.persistent
     return p
+
+
+def nlm_ops_per_candidate(f, c):
+    """Lane operations per pixel and search candidate of NL-means in the
+    separable form: per channel a difference and a fused square-add, 2f adds
+    for the horizontal and 2f for the vertical patch sum, the exponent
+    (scale, clamp, difference to the running minimum, multiply, exponential),
+    the running minimum, and per channel plus the denominator one
+    multiply-add."""
+    return 2 * c + 4 * f + 5 + 1 + (c + 1)
+
+
+def run_nlm(args):
+    """NL-means first stage: 16 x 512^2 grey, sigma 25, one batched launch per step."""
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+    assert torch.cuda.is_available(), "no GPU"
+    sigma, H, W, B = 25.0, 512, 512, args.batch
+    samples = [synth.gray_512(index=i, sigma=sigma) for i in range(B)]
+    imgs = [torch.from_numpy(s.noisy).cuda() for s in samples]
+    outs = [torch.empty((H, W), dtype=torch.float32, device="cuda") for _ in range(B)]
+    p = bm3d.nlm_params_default(sigma, 1)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    for _ in range(args.warmup):
+        bm3d.nlm_batch(imgs, sigma, p, outs, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        bm3d.nlm_batch(imgs, sigma, p, outs, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ms_launch = e0.elapsed_time(e1) / args.steps
+    mp = B * H * W / 1e6
+    log("nlm batched: %.3f ms/step, %.1f MP/s" % (dt * 1e3, mp / dt))
+    f, r = p.patch_radius, p.search_radius
+    # candidates inside the image for every pixel (clipped windows)
+    span = lambda n: sum(min(n - 1, i + r) - max(0, i - r) + 1 for i in range(n))
+    cand = span(H) * span(W) - H * W
+    work = B * cand * nlm_ops_per_candidate(f, 1)
+    achieved = work / (ms_launch * 1e-3)
+    ps = [synth.psnr(s.clean, o.cpu().numpy()) for s, o in zip(samples, outs)]
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import nlm as onlm
+        crop = samples[0].noisy[:192, :192]
+        n, t1 = 0, time.perf_counter()
+        while True:
+            onlm.nlm(crop, sigma)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= min(args.cpu_seconds, 10.0):
+                break
+        cpu = {"value": n * crop.size / 1e6 / el, "unit": "MP/s", "cores": 1, "kind": "oracle",
+               "sample": "%d x 192x192 crop of a 512x512 grey sigma=25 image, FP64 numpy oracle, %.1f s"
+                         % (n, el)}
+    res = {
+        "metric": "denoised MP/s (NL-means first stage, sigma=25)", "value": mp / dt, "unit": "MP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512 grey, sigma=25, 5x5 patches, 21x21 windows, h=10, batch of %d "
+                               "images per launch" % B, "batch": B, "patch_radius": f, "search_radius": r,
+                   "h": p.h},
+        "roofline": {"bound": "alu", "kernel": "nlm", "achieved": achieved / 1e12,
+                     "peak": PEAK["valu_ops"] / 1e12, "unit": "TOP/s",
+                     "frac": achieved / PEAK["valu_ops"], "traffic": None, "ms_per_launch": ms_launch,
+                     "work_per_launch": work},
+        "psnr_db": {"mean": float(np.mean(ps)), "min": float(np.min(ps))},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def run_batch64(args):
@@ -269,9 +346,10 @@ def main():
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving"],
+    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm"],
                     help="grey512: the headline 16 x 512^2 batch (default); batch64: the 64-image "
-                         "mixed batch; serving: the request loop against the FP32 single-image path")
+                         "mixed batch; serving: the request loop against the FP32 single-image path; "
+                         "nlm: the NL-means first stage on the 16 x 512^2 batch")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--slots", type=int, default=32, help="serving: requests in flight")
@@ -288,6 +366,8 @@ def main():
         return run_batch64(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "nlm":
+        return run_nlm(args)
 
     import torch
     from paper_2403_03488_amd import bm3d, synth
