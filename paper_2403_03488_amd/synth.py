@@ -264,3 +264,43 @@ def noise_crop(noise: np.ndarray, spec) -> np.ndarray:
 def crop_clean(canvases, spec):
     a = canvases[spec["kind"]]
     return np.ascontiguousarray(a[spec["y0"]:spec["y0"] + spec["h"], spec["x0"]:spec["x0"] + spec["w"]])
+
+
+# ------------------------------------------------------- network weights ----
+# Trained weights of the residual network (WED training, Section II) are not
+# available; both the HIP path and the oracle take these seeded stand-ins.
+
+
+def bf16_representable(a: np.ndarray) -> np.ndarray:
+    """float32 copy of `a` whose values are exactly representable in bfloat16
+    (round to nearest, ties to even, on the float32 bit pattern)."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def cnn_layers(layers: int = 10, channels: int = 3, features: int = 64, seed: int = 0,
+               residual_scale: float = 0.02):
+    """K layer dicts for the residual network: He-normal 3x3 kernels
+    (std sqrt(2 / fan_in)), rounded to bfloat16-representable values so that
+    every precision sees the same weights; small biases; inference-mode batch
+    normalisation statistics on the middle layers.  The last layer is scaled
+    so that the residual is a correction of a few grey levels (std
+    residual_scale * sqrt(1 / fan_in))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(layers):
+        cin = 2 * channels if k == 0 else features
+        cout = channels if k == layers - 1 else features
+        fan_in = 9 * cin
+        std = residual_scale * math.sqrt(1.0 / fan_in) if k == layers - 1 else math.sqrt(2.0 / fan_in)
+        L = {"weight": bf16_representable(rng.normal(0.0, std, (cout, cin, 3, 3))),
+             "bias": rng.normal(0.0, 0.02, cout).astype(np.float32)}
+        if 0 < k < layers - 1:
+            L.update(gamma=rng.uniform(0.8, 1.2, cout).astype(np.float32),
+                     beta=rng.normal(0.0, 0.05, cout).astype(np.float32),
+                     mean=rng.normal(0.0, 0.1, cout).astype(np.float32),
+                     var=rng.uniform(0.5, 1.5, cout).astype(np.float32),
+                     eps=1e-5)
+        out.append(L)
+    return out
