@@ -217,6 +217,96 @@ def run_nlm(args):
     print(json.dumps(res), flush=True)
 
 
+def run_cnn(args):
+    """Residual network behind the first stage (K = 10, colour, Table 3's
+    512 x 512 case): 16 images per call, one launch per layer."""
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+    assert torch.cuda.is_available(), "no GPU"
+    K, C, H, W, B = 10, 3, 512, 512, args.batch
+    layers = synth.cnn_layers(K, C, seed=1)
+    net = bm3d.Cnn(layers, C)
+    samples = [synth.colour_481x321(index=i) for i in range(B)]
+    rng = np.random.default_rng(0)
+    basics, noisys = [], []
+    for s in samples:
+        # 512 x 512 from the 481 x 321 colour family, tiled by reflection
+        cl = np.pad(s.clean, ((0, H - s.clean.shape[0]), (0, W - s.clean.shape[1]), (0, 0)), mode="reflect")
+        ny = np.pad(s.noisy, ((0, H - s.noisy.shape[0]), (0, W - s.noisy.shape[1]), (0, 0)), mode="reflect")
+        basics.append(torch.from_numpy((cl + rng.normal(0, 3, cl.shape)).astype(np.float32)).cuda())
+        noisys.append(torch.from_numpy(np.ascontiguousarray(ny)).cuda())
+    outs = [torch.empty((H, W, C), dtype=torch.float32, device="cuda") for _ in range(B)]
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    for _ in range(args.warmup):
+        net.restore(basics, noisys, outs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.restore(basics, noisys, outs, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the dominant kernel: the 64 -> 64 layers, K - 2 launches per pass
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        net.restore(basics, noisys, outs, stream=stream, layers=(1, K - 1))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_hidden = e0.elapsed_time(e1) / (args.steps * (K - 2))
+    net.restore(basics, noisys, outs, stream=stream)
+    torch.cuda.synchronize()
+    mp = B * H * W / 1e6
+    flops_pass = 2 * B * ocnn_macs(K, C, H, W)
+    flops_hidden = 2 * B * H * W * 9 * 64 * 64
+    achieved = flops_hidden / (ms_hidden * 1e-3)
+    log("cnn K=%d: %.3f ms/step (%d images), %.1f MP/s, %.1f TFLOP/s whole pass; hidden layer %.3f ms, "
+        "%.1f TFLOP/s" % (K, dt * 1e3, B, mp / dt, flops_pass / dt / 1e12, ms_hidden, achieved / 1e12))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import cnn as ocnn
+        b0, y0 = basics[0][:128, :128].cpu().numpy(), noisys[0][:128, :128].cpu().numpy()
+        n, t1 = 0, time.perf_counter()
+        while True:
+            ocnn.restore(b0, y0, layers)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= min(args.cpu_seconds, 10.0):
+                break
+        cpu = {"value": n * 128 * 128 / 1e6 / el, "unit": "MP/s", "cores": blas_threads(),
+               "kind": "oracle",
+               "sample": "%d x 128x128 colour crop, K=10, FP64 numpy oracle (BLAS tensordot), %.1f s" % (n, el)}
+    res = {
+        "metric": "restored MP/s (residual network x_hat = BM3D(y) + F(z), K=10, colour)", "value": mp / dt,
+        "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded random weights; trained weights not available)",
+        "config": {"workload": "512x512 colour, K=10 (2C->64, 8 x 64->64 with batch norm, 64->C), batch of %d "
+                               "images per call" % B, "batch": B, "layers": K,
+                   "gflop_per_image": flops_pass / B / 1e9},
+        "roofline": {"bound": "mfma", "kernel": "k_conv<1,4,false> (64->64 layer)", "achieved": achieved / 1e12,
+                     "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
+                     "traffic": None, "ms_per_launch": ms_hidden, "work_per_launch": flops_hidden},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def blas_threads():
+    """Threads of the BLAS numpy's tensordot runs on."""
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        return 1
+
+
+def ocnn_macs(K, C, H, W, F=64):
+    """Multiply-adds of the network on one H x W image (9 per input/output
+    channel pair, pixel and layer)."""
+    return 9 * H * W * (2 * C * F + (K - 2) * F * F + F * C)
+
+
 def run_batch64(args):
     """The mixed batch: 64 images of areas 128^2..1024^2 (aspect 1:1-2:1),
     half grey / half colour, sigma ~ U[10,50], one captured graph per step."""
@@ -346,7 +436,7 @@ def main():
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm"],
+    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm", "cnn"],
                     help="grey512: the headline 16 x 512^2 batch (default); batch64: the 64-image "
                          "mixed batch; serving: the request loop against the FP32 single-image path; "
                          "nlm: the NL-means first stage on the 16 x 512^2 batch")
@@ -366,6 +456,8 @@ def main():
         return run_batch64(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "cnn":
+        return run_cnn(args)
     if args.workload == "nlm":
         return run_nlm(args)
 

@@ -183,6 +183,65 @@ int bm3d_nlm(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_nl
 int bm3d_nlm_batch(const uint8_t* const* imgs, float* const* outs, int n, int h, int w, int c,
                    float sigma, const bm3d_nlm_params* p, bm3d_stream_t stream);
 
+/* ---- residual network behind the first stage (Section II) ----
+ * x_hat = BM3D(y) + 255 F(z), z = Concatenate(BM3D(y), y) / 255 (eqs. (2) and
+ * (3): the network learns the residual of the first-stage estimate from it
+ * and the observation).  F is a DnCNN-style stack of K 3x3 convolutions with
+ * zero padding (outputs keep the image size):
+ *   layer 1        2C -> 64 features, + bias, ReLU
+ *   layers 2..K-1  64 -> 64, + bias, batch normalisation, ReLU
+ *   layer K        64 -> C, + bias
+ * Any layer's bias or batch normalisation may be absent.  Weights are
+ * rounded to bfloat16 at creation; activations are stored in bfloat16
+ * between layers; products accumulate in FP32 and the normalisation, ReLU
+ * and the residual addition are FP32. */
+typedef struct {
+  const float* weight;   /* host [cout][cin][3][3] (cross-correlation taps), required */
+  const float* bias;     /* host [cout], or NULL */
+  const float* bn_gamma; /* host [cout] each, all four set or all NULL: inference-mode */
+  const float* bn_beta;  /*   gamma (x - mean) / sqrt(var + eps) + beta */
+  const float* bn_mean;
+  const float* bn_var;
+  float bn_eps;
+} bm3d_cnn_layer;
+
+typedef struct bm3d_cnn bm3d_cnn;
+
+/* Builds a network on the current device: `layers` = K (3..64) entries of
+ * host_layers, c = 1 or 3 image channels, features must be 64
+ * (BM3D_ERR_UNSUPPORTED otherwise).  Non-finite weights, biases or
+ * statistics, var + eps <= 0, or a partial normalisation give BM3D_ERR_ARG;
+ * nothing is allocated then.  The host arrays are read before the call
+ * returns; the network owns one device block of packed weights
+ * (BM3D_ERR_NOMEM if it cannot be allocated).  Synchronous. */
+int bm3d_cnn_create(int layers, int c, int features, const bm3d_cnn_layer* host_layers, bm3d_cnn** net);
+int bm3d_cnn_destroy(bm3d_cnn* net);
+
+/* Device workspace bm3d_cnn_restore needs for n images of h x w: two
+ * bfloat16 activation planes of 64 features (256 bytes per pixel). */
+int bm3d_cnn_workspace_bytes(int n, int h, int w, size_t* bytes);
+
+/* x_hat for n (1..64) images of one size: basic[i] device HWC float
+ * [h][w][c] (the first-stage estimate, [0,255] scale), noisy[i] device HWC
+ * uint8 (the observation), out[i] device HWC float, unclipped (may not alias
+ * basic[i]).  The three pointer arrays are host memory read before the call
+ * returns.  workspace: device memory of at least bm3d_cnn_workspace_bytes,
+ * 16-byte aligned (BM3D_ERR_WORKSPACE otherwise), overwritten.  Must be
+ * called on the device the network was created on.  Enqueues K launches on
+ * `stream`; allocates nothing. */
+int bm3d_cnn_restore(const bm3d_cnn* net, const float* const* basic, const uint8_t* const* noisy,
+                     float* const* out, int n, int h, int w, void* workspace, size_t workspace_bytes,
+                     bm3d_stream_t stream);
+
+/* Layers first .. last - 1 (0-based, 0 <= first < last <= K) of the same
+ * pass, for pipelines that split the network and for per-layer timing.
+ * Layer k > 0 reads the activations layer k - 1 left in the workspace (the
+ * caller keeps the workspace and arguments of the earlier part); only the
+ * last layer writes out.  Same arguments and errors as bm3d_cnn_restore. */
+int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basic, const uint8_t* const* noisy,
+                        float* const* out, int n, int h, int w, void* workspace, size_t workspace_bytes,
+                        int first, int last, bm3d_stream_t stream);
+
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
  * image's working buffers and a device table of image descriptors with

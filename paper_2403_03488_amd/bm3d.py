@@ -45,6 +45,12 @@ class NlmParams(ctypes.Structure):
     _fields_ = [("patch_radius", ctypes.c_int), ("search_radius", ctypes.c_int), ("h", ctypes.c_float)]
 
 
+class CnnLayer(ctypes.Structure):
+    _fields_ = [("weight", ctypes.c_void_p), ("bias", ctypes.c_void_p), ("bn_gamma", ctypes.c_void_p),
+                ("bn_beta", ctypes.c_void_p), ("bn_mean", ctypes.c_void_p), ("bn_var", ctypes.c_void_p),
+                ("bn_eps", ctypes.c_float)]
+
+
 class ImageDesc(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
                 ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
@@ -73,6 +79,13 @@ _SIGS = {
     "bm3d_nlm": (_i, [_vp, _i, _i, _i, _f, ctypes.POINTER(NlmParams), _vp, _vp]),
     "bm3d_nlm_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i, _i, _f,
                             ctypes.POINTER(NlmParams), _vp]),
+    "bm3d_cnn_create": (_i, [_i, _i, _i, ctypes.POINTER(CnnLayer), ctypes.POINTER(_vp)]),
+    "bm3d_cnn_destroy": (_i, [_vp]),
+    "bm3d_cnn_workspace_bytes": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "bm3d_cnn_restore": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i,
+                              _vp, _sz, _vp]),
+    "bm3d_cnn_run_layers": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i,
+                                 _vp, _sz, _i, _i, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -256,6 +269,83 @@ def nlm_batch(imgs, sigma: float, p: NlmParams | None = None, outs=None, stream=
     _check(_lib.bm3d_nlm_batch(ia, oa, n, h, w, c, float(sigma), ctypes.byref(p), _stream(stream)),
            "bm3d_nlm_batch")
     return outs
+
+
+# ------------------------------------------------------ residual network ---
+
+class Cnn:
+    """The residual network of bm3d_cnn_create: ``layers`` is a list of K
+    dicts of host arrays (weight [cout][cin][3][3], optional bias and
+    gamma/beta/mean/var/eps of batch normalisation).  Weights are copied to
+    the current device at construction."""
+
+    def __init__(self, layers, c: int, features: int = 64):
+        self.c, self.K = int(c), len(layers)
+        keep = []
+
+        def arr(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float32)
+            keep.append(a)
+            return a.ctypes.data
+
+        descs = (CnnLayer * self.K)()
+        for k, L in enumerate(layers):
+            bn = L.get("gamma") is not None
+            descs[k] = CnnLayer(arr(L["weight"]), arr(L.get("bias")), arr(L.get("gamma")), arr(L.get("beta")),
+                                arr(L.get("mean")), arr(L.get("var")), float(L.get("eps", 0.0)) if bn else 0.0)
+        h = ctypes.c_void_p()
+        _check(_lib.bm3d_cnn_create(self.K, self.c, int(features), descs, ctypes.byref(h)), "bm3d_cnn_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.bm3d_cnn_destroy(self._h)
+            self._h = None
+
+    @staticmethod
+    def workspace_bytes(n: int, h: int, w: int) -> int:
+        b = _sz()
+        _check(_lib.bm3d_cnn_workspace_bytes(int(n), int(h), int(w), ctypes.byref(b)), "bm3d_cnn_workspace_bytes")
+        return b.value
+
+    def restore(self, basics, noisys, outs=None, workspace=None, stream=None, layers=None):
+        """x_hat = basic + 255 F(basic, noisy) for up to 64 device images of
+        one shape (basic float32, noisy uint8, [h,w] or [h,w,c]).  Returns
+        the list of float32 outputs.  ``layers=(first, last)`` runs only
+        that range (bm3d_cnn_run_layers)."""
+        torch = _torch()
+        n = len(basics)
+        if n != len(noisys):
+            raise ValueError("restore: as many first-stage estimates as observations")
+        shape = tuple(basics[0].shape)
+        for t in list(basics) + list(noisys):
+            if tuple(t.shape) != shape:
+                raise ValueError("restore: images must share one shape")
+        c = 1 if len(shape) == 2 else shape[2]
+        if c != self.c:
+            raise ValueError("restore: the network was built for %d channels" % self.c)
+        h, w = shape[0], shape[1]
+        if outs is None:
+            outs = [torch.empty(shape, dtype=torch.float32, device=basics[0].device) for _ in range(n)]
+        need = self.workspace_bytes(n, h, w)
+        if workspace is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=basics[0].device)
+            workspace = self._ws
+        ba = (_vp * n)(*[_ptr(t, torch.float32, "basic") for t in basics])
+        na = (_vp * n)(*[_ptr(t, torch.uint8, "noisy") for t in noisys])
+        oa = (_vp * n)(*[_ptr(t, torch.float32, "out") for t in outs])
+        ws = _ptr(workspace, torch.uint8, "workspace")
+        if layers is None:
+            _check(_lib.bm3d_cnn_restore(self._h, ba, na, oa, n, h, w, ws, workspace.numel(), _stream(stream)),
+                   "bm3d_cnn_restore")
+        else:
+            _check(_lib.bm3d_cnn_run_layers(self._h, ba, na, oa, n, h, w, ws, workspace.numel(), int(layers[0]),
+                                            int(layers[1]), _stream(stream)), "bm3d_cnn_run_layers")
+        return outs
 
 
 def autotune(p: Params, cache_path: str | None = None) -> Params:

@@ -92,6 +92,59 @@ def test_nlm_defaults_and_validation(B):
         assert L.bm3d_nlm(fake, 64, 64, 1, 25.0, ref(bad), fake, None) == -1, field
 
 
+def test_cnn_validation_on_host(B):
+    # every rejected case fails before any device call
+    import numpy as np
+    from paper_2403_03488_amd import synth
+    L = B._lib
+    ref = ctypes.byref
+    assert ctypes.sizeof(B.CnnLayer) == 7 * 8
+    layers = synth.cnn_layers(4, 3)
+    keep = []
+
+    def descs(ls):
+        arr = (B.CnnLayer * len(ls))()
+        for k, d in enumerate(ls):
+            ptr = {}
+            for key in ("weight", "bias", "gamma", "beta", "mean", "var"):
+                a = d.get(key)
+                if a is not None:
+                    a = np.ascontiguousarray(a, np.float32)
+                    keep.append(a)
+                ptr[key] = None if a is None else a.ctypes.data
+            arr[k] = B.CnnLayer(ptr["weight"], ptr["bias"], ptr["gamma"], ptr["beta"], ptr["mean"],
+                                ptr["var"], float(d.get("eps", 0.0)))
+        return arr
+
+    h = ctypes.c_void_p()
+    good = descs(layers)
+    assert L.bm3d_cnn_create(4, 3, 64, good, None) == -1
+    assert L.bm3d_cnn_create(4, 3, 64, None, ref(h)) == -1
+    assert L.bm3d_cnn_create(2, 3, 64, good, ref(h)) == -1      # fewer than 3 layers
+    assert L.bm3d_cnn_create(4, 2, 64, good, ref(h)) == -1      # channels
+    assert L.bm3d_cnn_create(4, 3, 32, good, ref(h)) == -2      # only 64 features
+    assert L.bm3d_cnn_create(65, 3, 64, good, ref(h)) == -2
+    bad = [dict(d) for d in layers]
+    w = bad[1]["weight"].copy()
+    w[0, 0, 1, 1] = np.nan
+    bad[1]["weight"] = w
+    assert L.bm3d_cnn_create(4, 3, 64, descs(bad), ref(h)) == -1
+    bad = [dict(d) for d in layers]
+    bad[2] = dict(bad[2], var=None)                               # partial normalisation
+    assert L.bm3d_cnn_create(4, 3, 64, descs(bad), ref(h)) == -1
+    bad = [dict(d) for d in layers]
+    bad[2] = dict(bad[2], var=-np.ones(64, np.float32))           # var + eps <= 0
+    assert L.bm3d_cnn_create(4, 3, 64, descs(bad), ref(h)) == -1
+    assert not h.value
+    b = ctypes.c_size_t()
+    assert L.bm3d_cnn_workspace_bytes(3, 20, 30, ref(b)) == 0 and b.value == 3 * 20 * 30 * 256
+    assert L.bm3d_cnn_workspace_bytes(0, 20, 30, ref(b)) == -1
+    arr = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    fake = ctypes.c_void_p(0x1000)
+    assert L.bm3d_cnn_restore(None, arr, arr, arr, 2, 64, 64, fake, 1 << 30, None) == -1
+    assert L.bm3d_cnn_destroy(None) == -1
+
+
 def test_host_validation_rejects_before_enqueue(B):
     L = B._lib
     p = B.params_default(25.0)
