@@ -304,3 +304,39 @@ def cnn_layers(layers: int = 10, channels: int = 3, features: int = 64, seed: in
                      eps=1e-5)
         out.append(L)
     return out
+
+
+def unet_net(channels: int = 3, seed: int = 0, widths=(32, 64, 128, 256, 256), residual_scale: float = 0.02):
+    """Seeded weights of the flexible U-Net: per depthwise separable block a
+    depthwise 3x3 kernel (std sqrt(2/9)) with bias and a pointwise kernel
+    (std sqrt(2/cin)) with bias and inference-mode batch normalisation; per
+    decoder level a 2x2 deconvolution (std sqrt(2/cin)) with bias; a 1x1
+    output layer scaled to a small residual.  All kernels are
+    bfloat16-representable."""
+    rng = np.random.default_rng(seed)
+    f32 = lambda a: np.asarray(a, np.float32)
+
+    def block(ci, co):
+        return {"dw": bf16_representable(rng.normal(0.0, math.sqrt(2.0 / 9.0), (ci, 3, 3))),
+                "dw_bias": f32(rng.normal(0.0, 0.02, ci)),
+                "pw": bf16_representable(rng.normal(0.0, math.sqrt(2.0 / ci), (co, ci))),
+                "pw_bias": f32(rng.normal(0.0, 0.02, co)),
+                "pw_gamma": f32(rng.uniform(0.8, 1.2, co)), "pw_beta": f32(rng.normal(0.0, 0.05, co)),
+                "pw_mean": f32(rng.normal(0.0, 0.1, co)), "pw_var": f32(rng.uniform(0.5, 1.5, co)),
+                "pw_eps": 1e-5}
+
+    net = {"enc": [], "down": [], "up": [None] * 4, "dec": [None] * 4}
+    c = 2 * channels + 1
+    for i in range(4):
+        net["enc"].append(block(c, widths[i]))
+        net["down"].append(block(widths[i], widths[i + 1]))
+        c = widths[i + 1]
+    for i in range(4):
+        net["up"][i] = {"weight": bf16_representable(rng.normal(0.0, math.sqrt(2.0 / widths[i + 1]),
+                                                               (widths[i + 1], widths[i], 2, 2))),
+                        "bias": f32(rng.normal(0.0, 0.02, widths[i]))}
+        net["dec"][i] = block(widths[i], widths[i])
+    net["out"] = {"weight": bf16_representable(rng.normal(0.0, residual_scale * math.sqrt(1.0 / widths[0]),
+                                                          (channels, widths[0]))),
+                  "bias": f32(rng.normal(0.0, 0.02, channels))}
+    return net
