@@ -60,22 +60,43 @@ def work_models(h, w, S, cnt1, cnt2, c=1):
     }
 
 
-def measured_traffic(kernel, images, tile):
-    """HBM bytes per launch of `kernel` from the committed counter runs
-    (profiles/hbm_traffic_*.json), if they were taken on the current kernel
-    sources with the same filter tile; None otherwise."""
+# The sources each kernel family is compiled from: a counter record counts
+# only while these are unchanged.
+FAMILY_SOURCES = {"bm3d": "bm3d_*", "cnn": "cnn.hip"}
+
+
+def source_sha(family):
     import glob
     import hashlib
     src = "".join(open(f).read() for f in sorted(glob.glob(os.path.join(
-        ROOT, "paper_2403_03488_amd", "csrc", "*"))))
-    sha = hashlib.sha256(src.encode()).hexdigest()[:16]
+        ROOT, "paper_2403_03488_amd", "csrc", FAMILY_SOURCES[family]))))
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, images, tile, family="bm3d"):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/hbm_traffic_*.json), if they were taken on the current sources
+    of its kernel family with the same tile setting; None otherwise."""
+    import glob
+    sha = source_sha(family)
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
         rec = json.load(open(path))
-        if (rec.get("source_sha") == sha and rec.get("tile_refs") == tile
-                and kernel in rec.get("kernels", {})):
+        if (rec.get("family", "bm3d") == family and rec.get("source_sha") == sha
+                and rec.get("tile_refs") == tile and kernel in rec.get("kernels", {})):
             k = rec["kernels"][kernel]
             return images * (k["fetch_bytes_per_image"] + k["write_bytes_per_image"])
     return None
+
+
+def calibration_copy(torch):
+    """A 256 MiB device-to-device copy: the reference the byte counters of
+    the profiled kernels are scaled by."""
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def single_image_checks(torch, bm3d, synth, p, imgs, outs, samples, sigma, H, W, B):
@@ -236,6 +257,8 @@ def run_cnn(args):
         basics.append(torch.from_numpy((cl + rng.normal(0, 3, cl.shape)).astype(np.float32)).cuda())
         noisys.append(torch.from_numpy(np.ascontiguousarray(ny)).cuda())
     outs = [torch.empty((H, W, C), dtype=torch.float32, device="cuda") for _ in range(B)]
+    if args.calibrate_copy:
+        calibration_copy(torch)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     for _ in range(args.warmup):
@@ -286,7 +309,119 @@ def run_cnn(args):
                    "gflop_per_image": flops_pass / B / 1e9},
         "roofline": {"bound": "mfma", "kernel": "k_conv<1,4,false> (64->64 layer)", "achieved": achieved / 1e12,
                      "peak": PEAK["bf16"] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK["bf16"],
-                     "traffic": None, "ms_per_launch": ms_hidden, "work_per_launch": flops_hidden},
+                     "traffic": measured_traffic("hidden", B, 0, "cnn"), "ms_per_launch": ms_hidden,
+                     "work_per_launch": flops_hidden},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def unet_bytes(C, H, W, widths=(32, 64, 128, 256, 256)):
+    """Compulsory HBM bytes of one U-Net pass on one image: every launch
+    reads its input maps once and writes its output once (bf16 maps padded
+    to 8-channel words; FP32 estimate and output, uint8 observation)."""
+    hs, ws = [H], [W]
+    for _ in range(4):
+        hs.append((hs[-1] + 1) // 2)
+        ws.append((ws[-1] + 1) // 2)
+    px = [h * w for h, w in zip(hs, ws)]
+    m = lambda lv, ch: px[lv] * 2 * 8 * ((ch + 7) // 8)  # one bf16 map
+    cin = 2 * C + 1
+    tot = px[0] * (4 * C + C) + m(0, cin)               # first depthwise: images in, map out
+    tot += m(0, cin) + m(0, widths[0])                  # its pointwise
+    for i in range(4):
+        if i > 0:
+            tot += 2 * m(i, widths[i]) + 2 * m(i, widths[i])  # encoder depthwise + pointwise
+        tot += m(i, widths[i]) + m(i + 1, widths[i])          # stride-2 depthwise
+        tot += m(i + 1, widths[i]) + m(i + 1, widths[i + 1])  # its pointwise
+    for i in range(4):
+        tot += m(i + 1, widths[i + 1]) + 2 * m(i, widths[i])  # deconvolution: input, skip, output
+        tot += 4 * m(i, widths[i])                            # decoder depthwise + pointwise
+    tot += m(0, widths[0]) + px[0] * 8 * C                    # output layer: map, estimate, result
+    return tot
+
+
+def unet_macs(C, H, W, widths=(32, 64, 128, 256, 256)):
+    """Multiply-adds of the U-Net on one image: 9 per depthwise output, cin
+    per pointwise and deconvolution output."""
+    hs, ws = [H], [W]
+    for _ in range(4):
+        hs.append((hs[-1] + 1) // 2)
+        ws.append((ws[-1] + 1) // 2)
+    px = [h * w for h, w in zip(hs, ws)]
+    c, tot = 2 * C + 1, 0
+    for i in range(4):
+        tot += px[i] * (9 * c + c * widths[i]) + px[i + 1] * (9 * widths[i] + widths[i] * widths[i + 1])
+        c = widths[i + 1]
+    for i in range(4):
+        tot += 4 * px[i + 1] * widths[i + 1] * widths[i] + px[i] * (9 * widths[i] + widths[i] ** 2)
+    return tot + px[0] * widths[0] * C
+
+
+def run_unet(args):
+    """Flexible U-Net behind the first stage (colour, Table 3's 512 x 512
+    case): 16 images per call, 29 launches per pass."""
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+    assert torch.cuda.is_available(), "no GPU"
+    C, H, W, B, sigma = 3, 512, 512, args.batch, 25.0
+    weights = synth.unet_net(C, seed=1)
+    net = bm3d.Unet(weights, C)
+    rng = np.random.default_rng(0)
+    basics, noisys = [], []
+    for i in range(B):
+        s = synth.colour_481x321(index=i)
+        cl = np.pad(s.clean, ((0, H - s.clean.shape[0]), (0, W - s.clean.shape[1]), (0, 0)), mode="reflect")
+        ny = np.pad(s.noisy, ((0, H - s.noisy.shape[0]), (0, W - s.noisy.shape[1]), (0, 0)), mode="reflect")
+        basics.append(torch.from_numpy((cl + rng.normal(0, 3, cl.shape)).astype(np.float32)).cuda())
+        noisys.append(torch.from_numpy(np.ascontiguousarray(ny)).cuda())
+    outs = [torch.empty((H, W, C), dtype=torch.float32, device="cuda") for _ in range(B)]
+    if args.calibrate_copy:
+        calibration_copy(torch)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    for _ in range(args.warmup):
+        net.restore(basics, noisys, sigma, outs, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        net.restore(basics, noisys, sigma, outs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ms_pass = e0.elapsed_time(e1) / args.steps
+    mp = B * H * W / 1e6
+    flops = 2 * B * unet_macs(C, H, W)
+    traffic = B * unet_bytes(C, H, W)
+    log("unet: %.3f ms/step (%d images), %.1f MP/s, %.1f TFLOP/s, %.2f TB/s compulsory" % (
+        dt * 1e3, B, mp / dt, flops / dt / 1e12, traffic / (ms_pass * 1e-3) / 1e12))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import unet as ounet
+        b0, y0 = basics[0][:256, :256].cpu().numpy(), noisys[0][:256, :256].cpu().numpy()
+        n, t1 = 0, time.perf_counter()
+        while True:
+            ounet.restore(b0, y0, sigma, weights)
+            n += 1
+            el = time.perf_counter() - t1
+            if el >= min(args.cpu_seconds, 10.0):
+                break
+        cpu = {"value": n * 256 * 256 / 1e6 / el, "unit": "MP/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": "%d x 256x256 colour crop, FP64 numpy oracle (BLAS tensordot), %.1f s" % (n, el)}
+    res = {
+        "metric": "restored MP/s (flexible U-Net x_hat = BM3D(y) + F(z, sigma), colour)", "value": mp / dt,
+        "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded random weights; trained weights not available)",
+        "config": {"workload": "512x512 colour, sigma=25, widths 32/64/128/256/256, batch of %d images per call"
+                               % B, "batch": B, "gflop_per_image": flops / B / 1e9},
+        "roofline": {"bound": "hbm", "kernel": "whole pass (29 launches, stream-ordered)",
+                     "achieved": traffic / (ms_pass * 1e-3) / 1e9, "peak": PEAK["hbm_GBps"], "unit": "GB/s",
+                     "frac": traffic / (ms_pass * 1e-3) / 1e9 / PEAK["hbm_GBps"], "traffic": None,
+                     "ms_per_launch": ms_pass,
+                     "work_per_launch": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
@@ -436,7 +571,7 @@ def main():
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm", "cnn"],
+    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm", "cnn", "unet"],
                     help="grey512: the headline 16 x 512^2 batch (default); batch64: the 64-image "
                          "mixed batch; serving: the request loop against the FP32 single-image path; "
                          "nlm: the NL-means first stage on the 16 x 512^2 batch")
@@ -458,6 +593,8 @@ def main():
         return run_serving(args)
     if args.workload == "cnn":
         return run_cnn(args)
+    if args.workload == "unet":
+        return run_unet(args)
     if args.workload == "nlm":
         return run_nlm(args)
 
@@ -534,12 +671,7 @@ def main():
                  for k in work}
 
     if args.calibrate_copy:
-        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(torch)
     lat_ms, fp32_single, psnr32, psnrlo = [float("nan")], float("nan"), float("nan"), float("nan")
     if not args.quick:
         lat_ms, fp32_single, psnr32, psnrlo = single_image_checks(torch, bm3d, synth, p, imgs, outs,

@@ -242,6 +242,73 @@ int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basic, const ui
                         float* const* out, int n, int h, int w, void* workspace, size_t workspace_bytes,
                         int first, int last, bm3d_stream_t stream);
 
+/* ---- flexible lightweight U-Net (Section III, "Ours-FL") ----
+ * x_hat = BM3D(y) + 255 F(z), z = Concatenate(BM3D(y), y, sigma plane) / 255
+ * (the noise-level map of FFDNet).  F: 4 encoder levels i = 0..3, each a
+ * depthwise separable block DS(c -> w_i) whose output e_i is kept for the
+ * skip, then a stride-2 DS(w_i -> w_{i+1}); 4 decoder levels i = 3..0, each a
+ * 2x2 stride-2 deconvolution w_{i+1} -> w_i (+ bias, ReLU, cropped to e_i's
+ * size) plus e_i, then DS(w_i -> w_i); a 1x1 output layer w_0 -> C (+ bias).
+ * DS(ci -> co, s) = depthwise 3x3 (stride s, zero padding 1) + affine + ReLU,
+ * then pointwise ci -> co + affine + ReLU; "affine" is an optional bias then
+ * an optional inference-mode batch normalisation.  Default widths
+ * w = (32, 64, 128, 256, 256).  Pointwise, deconvolution and output weights
+ * are rounded to bfloat16 and contracted on the matrix cores with FP32
+ * accumulation; depthwise kernels stay FP32; activations are stored in
+ * bfloat16; the output is FP32. */
+typedef struct {
+  const float* dw;       /* host [ci][3][3], required */
+  const float* dw_bias;  /* host [ci] or NULL */
+  const float* dw_gamma; /* host [ci] each, all four or none */
+  const float* dw_beta;
+  const float* dw_mean;
+  const float* dw_var;
+  float dw_eps;
+  const float* pw;       /* host [co][ci], required */
+  const float* pw_bias;  /* host [co] or NULL */
+  const float* pw_gamma; /* host [co] each, all four or none */
+  const float* pw_beta;
+  const float* pw_mean;
+  const float* pw_var;
+  float pw_eps;
+} bm3d_ds_block;
+
+typedef struct {
+  bm3d_ds_block enc[4];      /* enc[0]: ci = 2C + 1 */
+  bm3d_ds_block down[4];     /* stride 2, w_i -> w_{i+1} */
+  bm3d_ds_block dec[4];      /* w_i -> w_i */
+  const float* up_weight[4]; /* host [w_{i+1}][w_i][2][2] (transposed-convolution layout) */
+  const float* up_bias[4];   /* host [w_i] or NULL */
+  const float* out_weight;   /* host [C][w_0] */
+  const float* out_bias;     /* host [C] or NULL */
+} bm3d_unet_weights;
+
+typedef struct bm3d_unet bm3d_unet;
+
+/* c = 1 or 3; widths: 5 host ints (multiples of 32, at most 256;
+ * BM3D_ERR_UNSUPPORTED otherwise) or NULL for the defaults.  Validates every
+ * array (finite values, var + eps > 0, complete normalisations:
+ * BM3D_ERR_ARG) before allocating one device block for the packed weights
+ * on the current device.  Host arrays are read before the call returns.
+ * Synchronous. */
+int bm3d_unet_create(int c, const int* widths, const bm3d_unet_weights* weights, bm3d_unet** net);
+int bm3d_unet_destroy(bm3d_unet* net);
+
+/* Device workspace for n images of h x w: the four skip maps and three
+ * working maps, bfloat16. */
+int bm3d_unet_workspace_bytes(const bm3d_unet* net, int n, int h, int w, size_t* bytes);
+
+/* x_hat for n (1..64) images of one size and one noise level sigma (>= 0,
+ * on the [0,255] scale): basic[i] device HWC float (first-stage estimate),
+ * noisy[i] device HWC uint8, out[i] device HWC float, unclipped (may not
+ * alias basic[i]); the pointer arrays are host memory.  workspace: device,
+ * 256-byte aligned, at least bm3d_unet_workspace_bytes (BM3D_ERR_WORKSPACE).
+ * Same device as creation.  Enqueues 29 launches on `stream`; allocates
+ * nothing. */
+int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic, const uint8_t* const* noisy,
+                      float* const* out, int n, int h, int w, float sigma, void* workspace,
+                      size_t workspace_bytes, bm3d_stream_t stream);
+
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
  * image's working buffers and a device table of image descriptors with

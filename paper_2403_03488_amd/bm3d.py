@@ -51,6 +51,19 @@ class CnnLayer(ctypes.Structure):
                 ("bn_eps", ctypes.c_float)]
 
 
+class DsBlock(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_void_p) for k in ("dw", "dw_bias", "dw_gamma", "dw_beta", "dw_mean", "dw_var")]
+                + [("dw_eps", ctypes.c_float)]
+                + [(k, ctypes.c_void_p) for k in ("pw", "pw_bias", "pw_gamma", "pw_beta", "pw_mean", "pw_var")]
+                + [("pw_eps", ctypes.c_float)])
+
+
+class UnetWeights(ctypes.Structure):
+    _fields_ = [("enc", DsBlock * 4), ("down", DsBlock * 4), ("dec", DsBlock * 4),
+                ("up_weight", ctypes.c_void_p * 4), ("up_bias", ctypes.c_void_p * 4),
+                ("out_weight", ctypes.c_void_p), ("out_bias", ctypes.c_void_p)]
+
+
 class ImageDesc(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
                 ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
@@ -86,6 +99,11 @@ _SIGS = {
                               _vp, _sz, _vp]),
     "bm3d_cnn_run_layers": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i,
                                  _vp, _sz, _i, _i, _vp]),
+    "bm3d_unet_create": (_i, [_i, ctypes.POINTER(_i), ctypes.POINTER(UnetWeights), ctypes.POINTER(_vp)]),
+    "bm3d_unet_destroy": (_i, [_vp]),
+    "bm3d_unet_workspace_bytes": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "bm3d_unet_restore": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i,
+                               _f, _vp, _sz, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -345,6 +363,94 @@ class Cnn:
         else:
             _check(_lib.bm3d_cnn_run_layers(self._h, ba, na, oa, n, h, w, ws, workspace.numel(), int(layers[0]),
                                             int(layers[1]), _stream(stream)), "bm3d_cnn_run_layers")
+        return outs
+
+
+def _images(basics, noisys, c, what):
+    n = len(basics)
+    if n != len(noisys):
+        raise ValueError("%s: as many first-stage estimates as observations" % what)
+    shape = tuple(basics[0].shape)
+    for t in list(basics) + list(noisys):
+        if tuple(t.shape) != shape:
+            raise ValueError("%s: images must share one shape" % what)
+    if (1 if len(shape) == 2 else shape[2]) != c:
+        raise ValueError("%s: the network was built for %d channels" % (what, c))
+    return n, shape
+
+
+class Unet:
+    """The flexible U-Net of bm3d_unet_create.  ``net`` is a dict of host
+    arrays: enc / down / dec lists of 4 depthwise separable blocks (keys dw,
+    dw_bias, pw, pw_bias and optional [dw_|pw_]gamma/beta/mean/var/eps),
+    up (4 dicts of weight [w_{i+1}][w_i][2][2] and bias) and out (weight
+    [C][w_0], bias)."""
+
+    def __init__(self, net, c: int, widths=None):
+        self.c = int(c)
+        keep = []
+
+        def arr(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float32)
+            keep.append(a)
+            return a.ctypes.data
+
+        def block(L):
+            b = DsBlock()
+            for pre in ("dw", "pw"):
+                setattr(b, pre, arr(L[pre]))
+                for k in ("bias", "gamma", "beta", "mean", "var"):
+                    setattr(b, pre + "_" + k, arr(L.get(pre + "_" + k)))
+                setattr(b, pre + "_eps", float(L.get(pre + "_eps", 0.0)))
+            return b
+
+        w = UnetWeights()
+        for i in range(4):
+            w.enc[i] = block(net["enc"][i])
+            w.down[i] = block(net["down"][i])
+            w.dec[i] = block(net["dec"][i])
+            w.up_weight[i] = arr(net["up"][i]["weight"])
+            w.up_bias[i] = arr(net["up"][i].get("bias"))
+        w.out_weight = arr(net["out"]["weight"])
+        w.out_bias = arr(net["out"].get("bias"))
+        wa = None if widths is None else (_i * 5)(*[int(x) for x in widths])
+        h = ctypes.c_void_p()
+        _check(_lib.bm3d_unet_create(self.c, wa, ctypes.byref(w), ctypes.byref(h)), "bm3d_unet_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.bm3d_unet_destroy(self._h)
+            self._h = None
+
+    def workspace_bytes(self, n: int, h: int, w: int) -> int:
+        b = _sz()
+        _check(_lib.bm3d_unet_workspace_bytes(self._h, int(n), int(h), int(w), ctypes.byref(b)),
+               "bm3d_unet_workspace_bytes")
+        return b.value
+
+    def restore(self, basics, noisys, sigma: float, outs=None, workspace=None, stream=None):
+        """x_hat = basic + 255 F(basic, noisy, sigma) for up to 64 device
+        images of one shape.  Returns the list of float32 outputs."""
+        torch = _torch()
+        n, shape = _images(basics, noisys, self.c, "restore")
+        h, w = shape[0], shape[1]
+        if outs is None:
+            outs = [torch.empty(shape, dtype=torch.float32, device=basics[0].device) for _ in range(n)]
+        need = self.workspace_bytes(n, h, w)
+        if workspace is None:
+            if self._ws is None or self._ws.numel() < need:
+                self._ws = torch.empty(need, dtype=torch.uint8, device=basics[0].device)
+            workspace = self._ws
+        ba = (_vp * n)(*[_ptr(t, torch.float32, "basic") for t in basics])
+        na = (_vp * n)(*[_ptr(t, torch.uint8, "noisy") for t in noisys])
+        oa = (_vp * n)(*[_ptr(t, torch.float32, "out") for t in outs])
+        _check(_lib.bm3d_unet_restore(self._h, ba, na, oa, n, h, w, float(sigma),
+                                      _ptr(workspace, torch.uint8, "workspace"), workspace.numel(),
+                                      _stream(stream)), "bm3d_unet_restore")
         return outs
 
 

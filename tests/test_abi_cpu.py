@@ -145,6 +145,36 @@ def test_cnn_validation_on_host(B):
     assert L.bm3d_cnn_destroy(None) == -1
 
 
+def test_unet_validation_on_host(B):
+    # rejected before any device call; nothing is allocated
+    import numpy as np
+    from paper_2403_03488_amd import synth
+    L = B._lib
+    ref = ctypes.byref
+    h = ctypes.c_void_p()
+    with pytest.raises(B.BM3DError):
+        B.Unet(synth.unet_net(3), 2)                                   # channels
+    with pytest.raises(B.BM3DError):
+        B.Unet(synth.unet_net(3, widths=(32, 64, 128, 256, 512)), 3, widths=(32, 64, 128, 256, 512))
+    with pytest.raises(B.BM3DError):
+        B.Unet(synth.unet_net(3, widths=(16, 32, 64, 128, 256)), 3, widths=(16, 32, 64, 128, 256))
+    bad = synth.unet_net(3)
+    bad["dec"][2]["dw"] = bad["dec"][2]["dw"].copy()
+    bad["dec"][2]["dw"][0, 0, 0] = np.inf
+    with pytest.raises(B.BM3DError):
+        B.Unet(bad, 3)
+    bad = synth.unet_net(3)
+    bad["enc"][1] = dict(bad["enc"][1], pw_var=None)                   # partial normalisation
+    with pytest.raises(B.BM3DError):
+        B.Unet(bad, 3)
+    assert L.bm3d_unet_create(3, None, None, ref(h)) == -1 and not h.value
+    b = ctypes.c_size_t()
+    assert L.bm3d_unet_workspace_bytes(None, 1, 8, 8, ref(b)) == -1
+    arr = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    assert L.bm3d_unet_restore(None, arr, arr, arr, 2, 64, 64, 25.0, ctypes.c_void_p(0x1000), 1 << 30, None) == -1
+    assert L.bm3d_unet_destroy(None) == -1
+
+
 def test_host_validation_rejects_before_enqueue(B):
     L = B._lib
     p = B.params_default(25.0)

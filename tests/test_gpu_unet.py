@@ -1,0 +1,122 @@
+"""Flexible U-Net through the C ABI against the FP64 oracle.
+
+The HIP path stores every activation in bfloat16 (relative error <= 2^-9)
+and contracts bfloat16 weights with FP32 accumulation; the oracle keeps FP64
+with the same bfloat16-representable weights.  An FP64 emulation of that
+storage rounding on these seeded networks gives max |error| 0.07-0.44 grey
+levels and an RMS error of 0.2-0.5 % of the residual's; the bar is max
+|error| <= 1.0 and RMS error <= 2 % of the residual.  A wrong tap, level,
+crop or skip moves the output by the size of the residual itself."""
+import numpy as np
+import pytest
+
+from oracle import unet as O
+from paper_2403_03488_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+MAX_ABS, REL_RMS = 1.0, 0.02
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2403_03488_amd import bm3d
+    return bm3d
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def inputs(h, w, c, seed):
+    rng = np.random.default_rng(seed)
+    clean = synth.mixed_colour_image(rng, h, w) if c == 3 else synth.smooth_texture_image(rng, h, w)
+    clean = clean.astype(np.float64)
+    noisy = synth.add_awgn_u8(clean, 25.0, rng)
+    basic = (clean + rng.normal(0, 3, clean.shape)).astype(np.float32)
+    return basic, noisy
+
+
+def run(net, basics, noisys, sigma):
+    bd = [torch.from_numpy(np.ascontiguousarray(b)).cuda() for b in basics]
+    nd = [torch.from_numpy(np.ascontiguousarray(y)).cuda() for y in noisys]
+    outs = net.restore(bd, nd, sigma)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy().astype(np.float64) for o in outs]
+
+
+def check(got, basic, noisy, sigma, weights, what):
+    ref = O.restore(basic, noisy, sigma, weights)
+    err = got - ref
+    rms_e, rms_f = np.sqrt((err ** 2).mean()), np.sqrt(((ref - basic) ** 2).mean())
+    log("%s: max|err| %.4f rms err %.4f rms residual %.3f" % (what, np.abs(err).max(), rms_e, rms_f))
+    assert np.isfinite(got).all()
+    assert np.abs(err).max() <= MAX_ABS
+    assert rms_e <= REL_RMS * rms_f
+
+
+@pytest.mark.parametrize("c,h,w,sigma", [(3, 96, 128, 25.0), (3, 77, 101, 50.0), (1, 64, 96, 15.0),
+                                         (1, 33, 17, 25.0)])
+def test_restore_matches_oracle(B, c, h, w, sigma):
+    weights = synth.unet_net(c, seed=h + c)
+    net = B.Unet(weights, c)
+    basic, noisy = inputs(h, w, c, seed=h * w)
+    got = run(net, [basic], [noisy], sigma)[0]
+    check(got, basic, noisy, sigma, weights, "c=%d %dx%d sigma %.0f" % (c, h, w, sigma))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 3), (2, 3), (17, 1), (5, 9, 3), (16, 16)])
+def test_small_and_degenerate_images(B, shape):
+    # maps shrink to 1 x 1 before the bottom level; every crop path
+    c = 3 if len(shape) == 3 else 1
+    weights = synth.unet_net(c, seed=5)
+    net = B.Unet(weights, c)
+    basic, noisy = inputs(shape[0], shape[1], c, seed=3)
+    got = run(net, [basic], [noisy], 25.0)[0]
+    check(got, basic, noisy, 25.0, weights, "shape %s" % (shape,))
+
+
+def test_other_widths_and_no_normalisation(B):
+    weights = synth.unet_net(3, seed=8, widths=(32, 32, 64, 64, 96))
+    for grp in ("enc", "down", "dec"):
+        for L in weights[grp]:
+            for k in ("gamma", "beta", "mean", "var", "eps"):
+                L.pop("pw_" + k)
+    net = B.Unet(weights, 3, widths=(32, 32, 64, 64, 96))
+    basic, noisy = inputs(50, 70, 3, seed=9)
+    got = run(net, [basic], [noisy], 30.0)[0]
+    check(got, basic, noisy, 30.0, weights, "widths 32/32/64/64/96")
+
+
+def test_zero_output_layer_returns_basic_exactly(B):
+    weights = synth.unet_net(3, seed=4)
+    weights["out"] = {"weight": np.zeros_like(weights["out"]["weight"]), "bias": np.zeros(3, np.float32)}
+    net = B.Unet(weights, 3)
+    basic, noisy = inputs(40, 60, 3, seed=6)
+    assert np.array_equal(run(net, [basic], [noisy], 25.0)[0], basic.astype(np.float64))
+
+
+def test_batch_equals_single(B):
+    weights = synth.unet_net(1, seed=7)
+    net = B.Unet(weights, 1)
+    pairs = [inputs(45, 70, 1, seed=40 + i) for i in range(3)]
+    batched = run(net, [p[0] for p in pairs], [p[1] for p in pairs], 20.0)
+    for (b, y), g in zip(pairs, batched):
+        assert np.array_equal(run(net, [b], [y], 20.0)[0], g)
+
+
+def test_full_size_batch_sampled(B):
+    # 16 colour 512 x 512 images in one call, as timed.  The receptive field
+    # spans the whole image (four downsamplings), so the oracle runs on two
+    # full images and every pixel is compared there; all outputs are finite.
+    c, n = 3, 16
+    weights = synth.unet_net(c, seed=1)
+    net = B.Unet(weights, c)
+    pairs = [inputs(512, 512, c, seed=200 + i) for i in range(n)]
+    outs = run(net, [p[0] for p in pairs], [p[1] for p in pairs], 25.0)
+    for o in outs:
+        assert np.isfinite(o).all()
+    for i in (0, 15):
+        check(outs[i], pairs[i][0], pairs[i][1], 25.0, weights, "512x512 image %d of 16" % i)
