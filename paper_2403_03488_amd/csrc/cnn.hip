@@ -43,25 +43,23 @@ constexpr int kHW = kTW + 2;                    // halo row length
 constexpr int kMaxBatch = 64;
 constexpr int kMaxLayers = 64;
 
-// A workgroup of NW waves owns a (2 NW) x 32 output tile: wave w computes
-// rows 2w and 2w + 1 (4 blocks of 16 pixels) for every output channel.
-constexpr int tile_rows(int nw) { return 2 * nw; }
-constexpr int halo_px(int nw) { return (tile_rows(nw) + 2) * kHW; }
+// A workgroup of NW waves owns an (NW PB / 2) x 32 output tile: wave w
+// computes PB blocks of 16 pixels (PB / 2 rows of two blocks) for every
+// output channel.
+constexpr int tile_rows(int nw, int pb) { return nw * pb / 2; }
+constexpr int halo_px(int nw, int pb) { return (tile_rows(nw, pb) + 2) * kHW; }
 
 // Layer input kinds: the two images (2C <= 6 channels in one 16-byte word
 // per pixel, 4 taps per contraction step) or 64 features (8 words per pixel,
-// half a tap per step).  In LDS a 64-feature pixel takes 9 words (one of
-// padding): word j of 16 consecutive pixels then lands in 16 distinct
-// 16-byte bank groups (9 is odd), and every fragment read is a per-lane base
-// plus a constant offset.
+// half a tap per step).
 constexpr int steps(int in) { return in == 0 ? 3 : 18; }
-constexpr int px_words(int in) { return in == 0 ? 1 : 9; }
-constexpr int data_words(int in, int nw) { return in == 0 ? halo_px(nw) : halo_px(nw) * 8; }
-constexpr int fetch_words(int in, int nw) { return (data_words(in, nw) + 64 * nw - 1) / (64 * nw); }
+constexpr int px_words(int in) { return in == 0 ? 1 : 8; }
+constexpr int data_words(int in, int nw, int pb) { return in == 0 ? halo_px(nw, pb) : halo_px(nw, pb) * 8; }
+constexpr int fetch_words(int in, int nw, int pb) { return (data_words(in, nw, pb) + 64 * nw - 1) / (64 * nw); }
 // LDS: weight fragments, the per-channel scale and shift (2 x 64 floats),
 // the halo.
-constexpr size_t lds_bytes(int in, int cob, int nw) {
-  return (size_t)(steps(in) * cob * 64 + 32 + halo_px(nw) * px_words(in)) * 16;
+constexpr size_t lds_bytes(int in, int cob, int nw, int pb) {
+  return (size_t)(steps(in) * cob * 64 + 32 + halo_px(nw, pb) * px_words(in)) * 16;
 }
 
 struct Io {
@@ -82,15 +80,21 @@ struct Shape {
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// LDS word of (halo pixel p, word j) of a 64-feature halo: the word's slot is
+// XOR-swizzled by p / 2, so word j of 8 consecutive pixels lands in 8
+// distinct 16-byte slots of the 64 banks.
+__device__ inline int halo_index(int p, int j) { return p * 8 + (j ^ ((p >> 1) & 7)); }
+
+
 // Data word q of a tile's halo, into registers (zero outside the image).
-template <int IN, int NW>
+template <int IN, int NW, int PB>
 __device__ inline u32x4 fetch_word(int q, const Io& io, const __bf16* act, const Shape& s, int img, int y0,
                                    int x0) {
   u32x4 v = {0u, 0u, 0u, 0u};
   const int p = IN == 0 ? q : q >> 3;
   const int hy = p / kHW, hx = p - hy * kHW;
   const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
-  if (q >= data_words(IN, NW) || gy < 0 || gy >= s.h || gx < 0 || gx >= s.w) return v;
+  if (q >= data_words(IN, NW, PB) || gy < 0 || gy >= s.h || gx < 0 || gx >= s.w) return v;
   const size_t pix = (size_t)gy * s.w + gx;
   if constexpr (IN == 1) {
     const __bf16* src = act + ((size_t)img * s.h * s.w + pix) * kF + (q & 7) * 8;
@@ -115,14 +119,15 @@ __device__ inline u32x4 fetch_word(int q, const Io& io, const __bf16* act, const
 }
 
 // IN: input kind; COB: output channel blocks of 16 (4, or 1 for the last
-// layer); LAST: residual epilogue; NW: waves; PERSIST: the grid is resident
+// layer); LAST: residual epilogue; NW: waves; PB: 16-pixel blocks per wave;
+// PERSIST: the grid is resident
 // and walks the tiles (weights loaded once, next halo fetched during the
 // contraction) instead of one tile per workgroup.
-template <int IN, int COB, bool LAST, int NW, bool PERSIST>
+template <int IN, int COB, bool LAST, int NW, int PB, bool PERSIST>
 __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf16* act_in, __bf16* act_out,
                                                   Shape s) {
   extern __shared__ __align__(16) u32x4 lds[];
-  constexpr int KS = steps(IN), NF = fetch_words(IN, NW), PW = px_words(IN), NT = 64 * NW;
+  constexpr int KS = steps(IN), NF = fetch_words(IN, NW, PB), NT = 64 * NW, TR = tile_rows(NW, PB);
   u32x4* sw = lds;
   float* saff = (float*)(lds + KS * COB * 64);  // scale [64], shift [64]
   u32x4* sh = lds + KS * COB * 64 + 32;
@@ -130,14 +135,11 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
 
   for (int i = tid; i < KS * COB * 64; i += NT) sw[i] = L.frag[i];
   if (tid < 2 * kF) saff[tid] = tid < kF ? L.scale[tid] : L.shift[tid - kF];
-  // LDS word of this lane's column, tap (0, 0), in each of the wave's 4
-  // pixel blocks; a fragment read adds a constant per (step, block)
-  int hb[4];
+  // halo pixel of this lane's column, tap (0, 0), in each of the wave's
+  // pixel blocks
+  int hb[PB];
 #pragma unroll
-  for (int pb = 0; pb < 4; ++pb) {
-    const int p = (2 * wv + (pb >> 1)) * kHW + (pb & 1) * 16 + (l & 15);
-    hb[pb] = p * PW + (IN == 0 ? 0 : (l >> 4));
-  }
+  for (int pb = 0; pb < PB; ++pb) hb[pb] = (wv * (PB / 2) + (pb >> 1)) * kHW + (pb & 1) * 16 + (l & 15);
 
   u32x4 reg[NF];
   auto fetch = [&](int tt) {
@@ -145,13 +147,13 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
     const int ty = r / s.tiles_x, tx = r - ty * s.tiles_x;
 #pragma unroll
     for (int k = 0; k < NF; ++k)
-      reg[k] = fetch_word<IN, NW>(tid + k * NT, io, act_in, s, img, ty * tile_rows(NW), tx * kTW);
+      reg[k] = fetch_word<IN, NW, PB>(tid + k * NT, io, act_in, s, img, ty * TR, tx * kTW);
   };
   auto store = [&]() {
 #pragma unroll
     for (int k = 0; k < NF; ++k) {
       const int q = tid + k * NT;
-      if (q < data_words(IN, NW)) sh[IN == 0 ? q : (q >> 3) * 9 + (q & 7)] = reg[k];
+      if (q < data_words(IN, NW, PB)) sh[IN == 0 ? q : halo_index(q >> 3, q & 7)] = reg[k];
     }
   };
 
@@ -165,59 +167,53 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
     const int tn = PERSIST ? t + (int)gridDim.x : s.total;
     if (PERSIST && tn < s.total) fetch(tn);
 
-    f32x4 acc[COB][4];
+    f32x4 acc[COB][PB];
 #pragma unroll
     for (int cb = 0; cb < COB; ++cb)
 #pragma unroll
-      for (int pb = 0; pb < 4; ++pb) acc[cb][pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    // fragments of step k: weights (A) and this wave's pixels (B)
+      for (int pb = 0; pb < PB; ++pb) acc[cb][pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // fragments of step k: weights (A) and this wave's pixels (B).  Image
+    // input: four taps per step, the lane group l / 16 takes tap 4k + l / 16;
+    // features: tap k / 2, words 4 (k % 2) + l / 16.
     auto frags = [&](int k, bf16x8* a, bf16x8* b) {
 #pragma unroll
       for (int cb = 0; cb < COB; ++cb) a[cb] = as_bf16x8(sw[(k * COB + cb) * 64 + l]);
 #pragma unroll
-      for (int pb = 0; pb < 4; ++pb) {
+      for (int pb = 0; pb < PB; ++pb) {
         if constexpr (IN == 0) {
           int tap = 4 * k + (l >> 4);
           tap = tap > 8 ? 8 : tap;  // taps 9..11 carry zero weights
           b[pb] = as_bf16x8(sh[hb[pb] + (tap / 3) * kHW + tap % 3]);
         } else {
           const int tap = k >> 1;
-          b[pb] = as_bf16x8(sh[hb[pb] + ((tap / 3) * kHW + tap % 3) * 9 + (k & 1) * 4]);
+          b[pb] = as_bf16x8(sh[halo_index(hb[pb] + (tap / 3) * kHW + tap % 3, (k & 1) * 4 + (l >> 4))]);
         }
       }
     };
-    bf16x8 a[COB], b[4];
+    bf16x8 a[COB], b[PB];
     frags(0, a, b);
-#pragma unroll
+#pragma unroll 2
     for (int k = 0; k < KS; ++k) {
       // read step k + 1 while step k's products issue
-      bf16x8 an[COB], bn[4];
-      if (k + 1 < KS) frags(k + 1, an, bn);
+      bf16x8 an[COB], bn[PB];
+      frags(k + 1 < KS ? k + 1 : k, an, bn);
 #pragma unroll
       for (int cb = 0; cb < COB; ++cb)
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb)
+        for (int pb = 0; pb < PB; ++pb)
           acc[cb][pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[cb], b[pb], acc[cb][pb], 0, 0, 0);
-      if (k + 1 < KS) {
 #pragma unroll
-        for (int cb = 0; cb < COB; ++cb) a[cb] = an[cb];
+      for (int cb = 0; cb < COB; ++cb) a[cb] = an[cb];
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) b[pb] = bn[pb];
-      }
+      for (int pb = 0; pb < PB; ++pb) b[pb] = bn[pb];
     }
 
-    if (PERSIST) {
-      // every wave is done with this halo: refill it before the epilogue's
-      // stores, so the wait for the fetched words covers no store
-      __syncthreads();
-      if (tn < s.total) store();
-    }
 
     const int img = t / s.per_img, r = t - img * s.per_img;
     const int ty = r / s.tiles_x, tx = r - ty * s.tiles_x;
 #pragma unroll
-    for (int pb = 0; pb < 4; ++pb) {
-      const int gy = ty * tile_rows(NW) + 2 * wv + (pb >> 1), gx = tx * kTW + (pb & 1) * 16 + (l & 15);
+    for (int pb = 0; pb < PB; ++pb) {
+      const int gy = ty * TR + wv * (PB / 2) + (pb >> 1), gx = tx * kTW + (pb & 1) * 16 + (l & 15);
       if (gy >= s.h || gx >= s.w) continue;
       const size_t pix = (size_t)gy * s.w + gx;
       if constexpr (!LAST) {
@@ -244,16 +240,18 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
       }
     }
     if (!PERSIST || tn >= s.total) break;
+    __syncthreads();  // every wave is done with this halo
+    store();
     __syncthreads();
     t = tn;
   }
 }
 
-template <int IN, int COB, bool LAST, int NW, bool PERSIST>
+template <int IN, int COB, bool LAST, int NW, int PB, bool PERSIST>
 static int launch(const LayerDev& L, const Io& io, const __bf16* in, __bf16* out, const Shape& s, int cus,
                   hipStream_t stream) {
-  const auto f = k_conv<IN, COB, LAST, NW, PERSIST>;
-  const size_t bytes = lds_bytes(IN, COB, NW);
+  const auto f = k_conv<IN, COB, LAST, NW, PB, PERSIST>;
+  const size_t bytes = lds_bytes(IN, COB, NW, PB);
   static int per_cu = 0;  // resident workgroups per CU, found on the first launch
   if (per_cu == 0) {
     if (hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
@@ -267,8 +265,8 @@ static int launch(const LayerDev& L, const Io& io, const __bf16* in, __bf16* out
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// The three layer kinds.
-constexpr int kNwHidden = 8, kNwThin = 4;
+// Waves and 16-pixel blocks per wave of every layer kind.
+constexpr int kNw = 8, kPb = 4;
 
 static uint16_t bf16_bits(float x) {
   uint32_t u;
@@ -417,14 +415,9 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
     io.noisy[i] = noisy[i];
     io.out[i] = out[i];
   }
-  // tilings of the thin (first, last) and the hidden layers
-  Shape s[2];
-  const int nws[2] = {kNwThin, kNwHidden};
-  for (int i = 0; i < 2; ++i) {
-    const long long tx = (w + kTW - 1) / kTW, ty = (h + tile_rows(nws[i]) - 1) / tile_rows(nws[i]);
-    if (tx * ty * n >= (1ll << 31) || (long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
-    s[i] = Shape{n, h, w, net->c, (int)tx, (int)(tx * ty), (int)(tx * ty * n)};
-  }
+  const long long tx = (w + kTW - 1) / kTW, ty = (h + tile_rows(kNw, kPb) - 1) / tile_rows(kNw, kPb);
+  if (tx * ty * n >= (1ll << 31) || (long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
+  const Shape s{n, h, w, net->c, (int)tx, (int)(tx * ty), (int)(tx * ty * n)};
   size_t need = 0;
   (void)bm3d_cnn_workspace_bytes(n, h, w, &need);
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 15)) return BM3D_ERR_WORKSPACE;
@@ -437,11 +430,11 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
   int e = 0;
   for (int k = first; k < last && e == 0; ++k) {
     if (k == 0)
-      e = launch<0, 4, false, kNwThin, false>(net->L[0], io, nullptr, act[0], s[0], net->cus, st);
+      e = launch<0, 4, false, kNw, kPb, true>(net->L[0], io, nullptr, act[0], s, net->cus, st);
     else if (k < K - 1)
-      e = launch<1, 4, false, kNwHidden, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s[1], net->cus, st);
+      e = launch<1, 4, false, kNw, kPb, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s, net->cus, st);
     else
-      e = launch<1, 1, true, kNwThin, false>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, s[0], net->cus, st);
+      e = launch<1, 1, true, kNw, kPb, true>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, s, net->cus, st);
   }
   return e == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
