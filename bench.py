@@ -427,6 +427,103 @@ def run_unet(args):
     print(json.dumps(res), flush=True)
 
 
+def run_vst(args):
+    """Variance-stabilising wrapper: 16 raw Poisson-Gaussian 512 x 512 grey
+    images (alpha 1.5, sigma 2, up to 150 counts); per step the forward map
+    over the batch, the batched BM3D pass (captured graph) at the 8-bit
+    noise level, and the unbiased inverse."""
+    import torch
+    from paper_2403_03488_amd import bm3d, synth
+    assert torch.cuda.is_available(), "no GPU"
+    H, W, B, alpha, sigma, peak = 512, 512, args.batch, 1.5, 2.0, 150.0
+    rng = np.random.default_rng(0)
+    raw = np.empty((B, H, W), np.float32)
+    for i in range(B):
+        x = synth.gray_512(index=i).clean.astype(np.float64) / 255.0 * peak
+        raw[i] = alpha * rng.poisson(x / alpha) + rng.normal(0.0, sigma, x.shape)
+    fmax = 2.0 / alpha * math.sqrt(max(alpha * float(raw.max()) + 0.375 * alpha * alpha + sigma * sigma, 0.0))
+    g = bm3d.GatParams(alpha, sigma, 0.0, 235.0 / fmax, 10.0)
+    sig = bm3d.gat_noise_level(g.scale)
+    zd = torch.from_numpy(raw).cuda()
+    u = torch.empty((B, H, W), dtype=torch.uint8, device="cuda")
+    d = torch.empty((B, H, W), dtype=torch.float32, device="cuda")
+    xh = torch.empty_like(d)
+    p = tuned_params(args, bm3d, sig, 0)
+    plan = bm3d.Batch([u[i] for i in range(B)], [d[i] for i in range(B)], [sig] * B, p)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    if args.calibrate_copy:
+        calibration_copy(torch)
+    bm3d.gat_forward(zd, g, out=u, stream=stream)
+    torch.cuda.synchronize()
+    plan.capture(stream)
+
+    def step():
+        bm3d.gat_forward(zd, g, out=u, stream=stream)
+        plan.launch(stream)
+        bm3d.gat_inverse(d, g, out=xh, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the wrapper's own kernels, timed alone with HIP events on their stream
+    reps = 50
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    for _ in range(reps):
+        bm3d.gat_forward(zd, g, out=u, stream=stream)
+    e1.record(stream)
+    for _ in range(reps):
+        bm3d.gat_inverse(d, g, out=xh, stream=stream)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    ms_f, ms_i = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+    n = B * H * W
+    bytes_f, bytes_i = 5 * n, 8 * n  # float in + u8 out; float in + float out
+    mp = n / 1e6
+    x = np.stack([synth.gray_512(index=i).clean.astype(np.float64) / 255.0 * peak for i in range(B)])
+    rmse = lambda a: float(np.sqrt(np.mean((a - x) ** 2)))
+    out = xh.cpu().numpy().astype(np.float64)
+    log("vst: %.3f ms/step (%d images), %.1f MP/s; forward %.1f us (%.0f GB/s), inverse %.1f us (%.0f GB/s); "
+        "rmse raw %.2f -> %.2f" % (dt * 1e3, B, mp / dt, ms_f * 1e3, bytes_f / ms_f / 1e6, ms_i * 1e3,
+                                    bytes_i / ms_i / 1e6, rmse(raw), rmse(out)))
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import vst as ovst
+        n_cpu, t1 = 0, time.perf_counter()
+        while True:
+            uu = ovst.forward_u8_f32(raw[0], alpha, sigma, 0.0, g.scale, g.offset)
+            ovst.restore_from_u8(uu.astype(np.float64), alpha, sigma, 0.0, g.scale, g.offset)
+            n_cpu += 1
+            el = time.perf_counter() - t1
+            if el >= min(args.cpu_seconds, 5.0):
+                break
+        cpu = {"value": n_cpu * H * W / 1e6 / el, "unit": "MP/s", "cores": 1, "kind": "oracle",
+               "sample": "%d x one 512x512 image through the oracle's forward map and inverse (the BM3D "
+                         "step excluded), numpy, %.1f s" % (n_cpu, el)}
+    res = {
+        "metric": "restored MP/s (raw Poisson-Gaussian: GAT, BM3D, unbiased inverse)", "value": mp / dt,
+        "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16+int8",
+        "data": "synthetic",
+        "config": {"workload": "16 raw 512x512 grey images, alpha=1.5, sigma=2, up to 150 counts; BM3D at the "
+                               "8-bit noise level %.2f" % sig, "batch": B, "alpha": alpha, "sigma": sigma,
+                   "scale": g.scale, "offset": g.offset},
+        "roofline": {"bound": "hbm", "kernel": "k_inverse (unbiased inverse)", "achieved": bytes_i / ms_i / 1e6,
+                     "peak": PEAK["hbm_GBps"], "unit": "GB/s", "frac": bytes_i / ms_i / 1e6 / PEAK["hbm_GBps"],
+                     "traffic": None, "ms_per_launch": ms_i, "work_per_launch": bytes_i,
+                     "forward": {"ms_per_launch": ms_f, "achieved": bytes_f / ms_f / 1e6}},
+        "rmse": {"raw": rmse(raw), "restored": rmse(out)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def blas_threads():
     """Threads of the BLAS numpy's tensordot runs on."""
     try:
@@ -571,7 +668,7 @@ def main():
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (HBM counter calibration)")
-    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm", "cnn", "unet"],
+    ap.add_argument("--workload", default="grey512", choices=["grey512", "batch64", "serving", "nlm", "cnn", "unet", "vst"],
                     help="grey512: the headline 16 x 512^2 batch (default); batch64: the 64-image "
                          "mixed batch; serving: the request loop against the FP32 single-image path; "
                          "nlm: the NL-means first stage on the 16 x 512^2 batch")
@@ -595,6 +692,8 @@ def main():
         return run_cnn(args)
     if args.workload == "unet":
         return run_unet(args)
+    if args.workload == "vst":
+        return run_vst(args)
     if args.workload == "nlm":
         return run_nlm(args)
 

@@ -309,6 +309,46 @@ int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic, const uin
                       float* const* out, int n, int h, int w, float sigma, void* workspace,
                       size_t workspace_bytes, bm3d_stream_t stream);
 
+/* ---- variance-stabilising wrapper for raw Poisson-Gaussian data ----
+ * The observation model y = x + n (eq. (1)) holds after a variance-
+ * stabilising transform (Introduction).  For z = alpha p + n,
+ * p ~ Poisson(x / alpha), n ~ N(mu, sigma^2), the generalised Anscombe
+ * transform f(z) = (2/alpha) sqrt(max(alpha z + 3/8 alpha^2 + sigma^2 -
+ * alpha mu, 0)) gives unit-variance noise; the wrapper stores it on the
+ * denoisers' 8-bit scale, u = clip(rint(scale f(z) + offset), 0, 255)
+ * (noise level sqrt(scale^2 + 1/12) there), and maps a denoised u_hat back
+ * with the closed-form approximation of the exact unbiased inverse:
+ * D = (u_hat - offset) / scale, x_hat = alpha max(I(D), 0) + mu for
+ * D >= 2 sqrt(3/8) (else mu), I(D) = D^2/4 + sqrt(3/2)/4 D^-1 - 11/8 D^-2
+ * + 5/8 sqrt(3/2) D^-3 - 1/8 - (sigma/alpha)^2. */
+typedef struct {
+  float alpha;  /* Poisson gain, > 0 */
+  float sigma;  /* Gaussian standard deviation, >= 0 */
+  float mu;     /* Gaussian mean */
+  float scale;  /* 8-bit units per unit of f, > 0 */
+  float offset; /* 8-bit code of f = 0 */
+} bm3d_gat_params;
+
+/* raw: device float [n] (any layout); out: device uint8 [n].  The code is
+ * computed in FP32 with one rounding per operation, in the order
+ * a z + c, max 0, sqrt, k s + offset, round half to even, clamp, where
+ * a = alpha, c = 3/8 alpha^2 + sigma^2 - alpha mu, k = 2 scale / alpha are
+ * rounded to FP32 from double.  Invalid parameters: BM3D_ERR_ARG. */
+int bm3d_gat_forward(const float* raw, long long n, const bm3d_gat_params* g, uint8_t* out,
+                     bm3d_stream_t stream);
+/* stab: device float [n] (a denoised 8-bit-scale image); out: device float
+ * [n], may equal stab.  FP32. */
+int bm3d_gat_inverse(const float* stab, long long n, const bm3d_gat_params* g, float* out,
+                     bm3d_stream_t stream);
+/* sqrt(scale^2 + 1/12): the noise level to denoise the 8-bit image with. */
+float bm3d_gat_noise_level(float scale);
+/* forward into stab (device uint8 [h][w][c]), bm3d_denoise at
+ * bm3d_gat_noise_level(scale) into out, inverse in place: out = x_hat
+ * (device float HWC).  params as for bm3d_denoise (its workspace included);
+ * allocates nothing. */
+int bm3d_vst_denoise(const float* raw, int h, int w, int c, const bm3d_gat_params* g, const bm3d_params* params,
+                     uint8_t* stab, float* out, bm3d_stream_t stream);
+
 /* ---- batched pass: many images of different sizes in one launch per stage ----
  * A plan fixes the image shapes and sigmas; it owns device memory for every
  * image's working buffers and a device table of image descriptors with

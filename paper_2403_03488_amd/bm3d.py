@@ -64,6 +64,11 @@ class UnetWeights(ctypes.Structure):
                 ("out_weight", ctypes.c_void_p), ("out_bias", ctypes.c_void_p)]
 
 
+class GatParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_float), ("sigma", ctypes.c_float), ("mu", ctypes.c_float),
+                ("scale", ctypes.c_float), ("offset", ctypes.c_float)]
+
+
 class ImageDesc(ctypes.Structure):
     _fields_ = [("img", ctypes.c_void_p), ("out", ctypes.c_void_p), ("h", ctypes.c_int),
                 ("w", ctypes.c_int), ("c", ctypes.c_int), ("sigma", ctypes.c_float)]
@@ -104,6 +109,10 @@ _SIGS = {
     "bm3d_unet_workspace_bytes": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
     "bm3d_unet_restore": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i,
                                _f, _vp, _sz, _vp]),
+    "bm3d_gat_forward": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(GatParams), _vp, _vp]),
+    "bm3d_gat_inverse": (_i, [_vp, ctypes.c_longlong, ctypes.POINTER(GatParams), _vp, _vp]),
+    "bm3d_gat_noise_level": (_f, [_f]),
+    "bm3d_vst_denoise": (_i, [_vp, _i, _i, _i, ctypes.POINTER(GatParams), _PP, _vp, _vp, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
@@ -452,6 +461,60 @@ class Unet:
                                       _ptr(workspace, torch.uint8, "workspace"), workspace.numel(),
                                       _stream(stream)), "bm3d_unet_restore")
         return outs
+
+
+# ------------------------------------------------ variance stabilisation ---
+
+def gat_noise_level(scale: float) -> float:
+    return float(_lib.bm3d_gat_noise_level(float(scale)))
+
+
+def gat_forward(raw, g: GatParams, out=None, stream=None):
+    """8-bit stabilised code of a device float tensor (any shape)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(raw.shape, dtype=torch.uint8, device=raw.device)
+    if out.numel() != raw.numel():
+        raise ValueError("gat_forward: out must have raw's size")
+    _check(_lib.bm3d_gat_forward(_ptr(raw, torch.float32, "raw"), raw.numel(), ctypes.byref(g),
+                                 _ptr(out, torch.uint8, "out"), _stream(stream)), "bm3d_gat_forward")
+    return out
+
+
+def gat_inverse(stab, g: GatParams, out=None, stream=None):
+    """Unbiased inverse of a denoised 8-bit-scale device float tensor."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(stab.shape, dtype=torch.float32, device=stab.device)
+    if out.numel() != stab.numel():
+        raise ValueError("gat_inverse: out must have stab's size")
+    _check(_lib.bm3d_gat_inverse(_ptr(stab, torch.float32, "stab"), stab.numel(), ctypes.byref(g),
+                                 _ptr(out, torch.float32, "out"), _stream(stream)), "bm3d_gat_inverse")
+    return out
+
+
+def vst_denoise(raw, g: GatParams, p: Params | None = None, out=None, stab=None, workspace=None, stream=None):
+    """x_hat of a raw Poisson-Gaussian device image (float [h,w] or
+    [h,w,3]): stabilise, BM3D at the 8-bit noise level, unbiased inverse."""
+    torch = _torch()
+    h, w = raw.shape[0], raw.shape[1]
+    c = 1 if raw.dim() == 2 else raw.shape[2]
+    p = (p or params_default(gat_noise_level(g.scale))).copy()
+    need = workspace_size(h, w, c, p)
+    if need == 0:
+        raise BM3DError(-1, "bm3d_workspace_size")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=raw.device)
+    p.workspace = workspace.data_ptr()
+    p.workspace_bytes = workspace.numel()
+    if out is None:
+        out = torch.empty(raw.shape, dtype=torch.float32, device=raw.device)
+    if stab is None:
+        stab = torch.empty(raw.shape, dtype=torch.uint8, device=raw.device)
+    _check(_lib.bm3d_vst_denoise(_ptr(raw, torch.float32, "raw"), h, w, c, ctypes.byref(g), ctypes.byref(p),
+                                 _ptr(stab, torch.uint8, "stab"), _ptr(out, torch.float32, "out"), _stream(stream)),
+           "bm3d_vst_denoise")
+    return out
 
 
 def autotune(p: Params, cache_path: str | None = None) -> Params:

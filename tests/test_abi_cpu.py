@@ -175,6 +175,25 @@ def test_unet_validation_on_host(B):
     assert L.bm3d_unet_destroy(None) == -1
 
 
+def test_vst_validation_on_host(B):
+    L = B._lib
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    for bad in ((0.0, 1.0, 0.0, 10.0, 0.0), (1.0, -1.0, 0.0, 10.0, 0.0), (1.0, 1.0, 0.0, 0.0, 0.0),
+                (float("nan"), 1.0, 0.0, 10.0, 0.0), (1.0, 1.0, float("inf"), 10.0, 0.0)):
+        g = B.GatParams(*bad)
+        assert L.bm3d_gat_forward(fake, 16, ctypes.byref(g), fake, None) == -1, bad
+        assert L.bm3d_gat_inverse(fake, 16, ctypes.byref(g), fake, None) == -1, bad
+    g = B.GatParams(1.0, 1.0, 0.0, 10.0, 0.0)
+    assert L.bm3d_gat_forward(None, 16, ctypes.byref(g), fake, None) == -1
+    assert L.bm3d_gat_forward(fake, -1, ctypes.byref(g), fake, None) == -1
+    assert L.bm3d_gat_forward(fake, 0, ctypes.byref(g), fake, None) == 0  # nothing to do
+    assert L.bm3d_gat_inverse(fake, 16, None, fake, None) == -1
+    p = B.params_default(25.0)
+    assert L.bm3d_vst_denoise(fake, 0, 64, 1, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -1
+    assert L.bm3d_vst_denoise(fake, 64, 64, 2, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -1
+    assert abs(L.bm3d_gat_noise_level(6.0) - math.sqrt(36 + 1 / 12)) < 1e-5
+
+
 def test_host_validation_rejects_before_enqueue(B):
     L = B._lib
     p = B.params_default(25.0)
