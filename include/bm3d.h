@@ -303,7 +303,7 @@ int bm3d_unet_workspace_bytes(const bm3d_unet* net, int n, int h, int w, size_t*
  * noisy[i] device HWC uint8, out[i] device HWC float, unclipped (may not
  * alias basic[i]); the pointer arrays are host memory.  workspace: device,
  * 256-byte aligned, at least bm3d_unet_workspace_bytes (BM3D_ERR_WORKSPACE).
- * Same device as creation.  Enqueues 29 launches on `stream`; allocates
+ * Same device as creation.  Enqueues 30 launches on `stream`; allocates
  * nothing. */
 int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic, const uint8_t* const* noisy,
                       float* const* out, int n, int h, int w, float sigma, void* workspace,

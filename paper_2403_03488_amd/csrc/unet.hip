@@ -7,9 +7,9 @@
 //
 // Activations are NHWC bfloat16, each pixel a whole number of 16-byte words
 // (8 channels).  Two kernels carry the network:
+//   k_pack  z as one bfloat16 word per pixel (2C + 1 <= 7 channels + zero).
 //   k_dw  depthwise 3x3 (stride 1 or 2, zero padding) + per-channel affine +
-//         ReLU on the vector ALUs, one thread per output word; the first one
-//         reads the two images and the sigma plane directly.
+//         ReLU on the vector ALUs, one thread per output word.
 //   k_pw  every 1x1 product on the bf16 matrix cores
 //         (v_mfma_f32_16x16x32_bf16, FP32 accumulation): output columns are
 //         the rows of the product and pixels its columns, a lane's 8
@@ -64,10 +64,35 @@ struct PwDev {
   int ksteps, groups, N, co;
 };
 
+// ------------------------------------------------------------------ input ---
+// z = (estimate channels, observation channels, sigma plane) / 255, zeros
+// after, rounded to bfloat16 like every activation: one word per pixel.
+__global__ void __launch_bounds__(kDwThreads) k_pack(Io io, float zsig, Act out, int n, int C) {
+  const long long total = (long long)n * out.h * out.w;
+  for (long long pix = (long long)blockIdx.x * kDwThreads + threadIdx.x; pix < total;
+       pix += (long long)gridDim.x * kDwThreads) {
+    const int img = (int)(pix / ((long long)out.h * out.w));
+    const size_t q = (size_t)(pix - (long long)img * out.h * out.w) * C;
+    const float* b = io.basic[img] + q;
+    const uint8_t* y = io.noisy[img] + q;
+    bf16x8 o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      float z = 0.f;
+      if (e < C)
+        z = b[e] / 255.f;
+      else if (e < 2 * C)
+        z = (float)y[e - C] / 255.f;
+      else if (e == 2 * C)
+        z = zsig;
+      o[e] = (__bf16)z;
+    }
+    *(u32x4*)(out.p + (size_t)pix * 8) = __builtin_bit_cast(u32x4, o);
+  }
+}
+
 // ------------------------------------------------------------- depthwise ---
-template <bool IMG>
-__global__ void __launch_bounds__(kDwThreads) k_dw(DwDev L, Io io, float zsig, Act in, Act out, int n, int C,
-                                                   int stride) {
+__global__ void __launch_bounds__(kDwThreads) k_dw(DwDev L, Act in, Act out, int n, int stride) {
   __shared__ float sw[kMaxWidth * 9];
   __shared__ float saf[2 * kMaxWidth];
   const int cp = out.cw * 8;
@@ -88,29 +113,10 @@ __global__ void __launch_bounds__(kDwThreads) k_dw(DwDev L, Io io, float zsig, A
       const int iy = oy * stride + tap / 3 - 1, ix = ox * stride + tap % 3 - 1;
       if (iy < 0 || iy >= in.h || ix < 0 || ix >= in.w) continue;
       float v[8];
-      if constexpr (IMG) {
-        // z = (estimate channels, observation channels, sigma plane) / 255
-        const size_t q = ((size_t)iy * in.w + ix) * C;
-        const float* b = io.basic[img] + q;
-        const uint8_t* y = io.noisy[img] + q;
+      const u32x4 wd = *(const u32x4*)(in.p + (((size_t)img * in.h + iy) * in.w + ix) * (in.cw * 8) + j * 8);
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, wd);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          float z = 0.f;
-          if (e < C)
-            z = b[e] / 255.f;
-          else if (e < 2 * C)
-            z = (float)y[e - C] / 255.f;
-          else if (e == 2 * C)
-            z = zsig;
-          v[e] = z;
-        }
-      } else {
-        const u32x4 wd =
-            *(const u32x4*)(in.p + (((size_t)img * in.h + iy) * in.w + ix) * (in.cw * 8) + j * 8);
-        const bf16x8 bv = __builtin_bit_cast(bf16x8, wd);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (float)bv[e];
-      }
+      for (int e = 0; e < 8; ++e) v[e] = (float)bv[e];
 #pragma unroll
       for (int e = 0; e < 8; ++e) acc[e] = fmaf(sw[(j * 8 + e) * 9 + tap], v[e], acc[e]);
     }
@@ -484,13 +490,20 @@ Plan plan(const int* W, int cin, int n, int h, int w) {
   return p;
 }
 
-template <bool IMG>
-int launch_dw(const DwDev& L, const Io& io, float zsig, Act in, Act out, int n, int C, int stride, int cus,
-              hipStream_t st) {
-  const long long total = (long long)n * out.h * out.w * out.cw;
-  const long long blocks = (total + kDwThreads - 1) / kDwThreads;
-  const int grid = (int)std::min<long long>(blocks, (long long)cus * 16);
-  hipLaunchKernelGGL(k_dw<IMG>, dim3(grid), dim3(kDwThreads), 0, st, L, io, zsig, in, out, n, C, stride);
+int grid_of(long long items, int cus) {
+  const long long blocks = (items + kDwThreads - 1) / kDwThreads;
+  return (int)std::min<long long>(blocks, (long long)cus * 16);
+}
+
+int launch_pack(const Io& io, float zsig, Act out, int n, int C, int cus, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_of((long long)n * out.h * out.w, cus)), dim3(kDwThreads), 0, st, io, zsig,
+                     out, n, C);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_dw(const DwDev& L, Act in, Act out, int n, int stride, int cus, hipStream_t st) {
+  hipLaunchKernelGGL(k_dw, dim3(grid_of((long long)n * out.h * out.w * out.cw, cus)), dim3(kDwThreads), 0, st, L,
+                     in, out, n, stride);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -543,18 +556,16 @@ extern "C" int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic
   hipStream_t st = (hipStream_t)stream;
   const float zsig = sigma / 255.f;
   const Act none{nullptr, 0, 0, 0};
-  const Act img{nullptr, h, w, 1};
-  int e = 0;
-  // encoders
-  Act x = img;
+  // z into the deconvolution buffer (free until the decoders), then encoders
+  Act x = act(p.Y, 0, cin);
+  int e = launch_pack(io, zsig, x, n, C, net->cus, st);
   for (int i = 0; i < 4 && e == 0; ++i) {
     const Act t = act(p.T, i, i == 0 ? cin : W[i]);
-    e = i == 0 ? launch_dw<true>(net->dw_enc[0], io, zsig, img, t, n, C, 1, net->cus, st)
-               : launch_dw<false>(net->dw_enc[i], io, zsig, x, t, n, C, 1, net->cus, st);
+    e = launch_dw(net->dw_enc[i], x, t, n, 1, net->cus, st);
     const Act ei = act(p.e[i], i, W[i]);
     if (e == 0) e = launch_pw<EP_PLAIN>(net->pw_enc[i], io, t, ei, none, n, C, st);
     const Act t2 = act(p.T, i + 1, W[i]);
-    if (e == 0) e = launch_dw<false>(net->dw_down[i], io, zsig, ei, t2, n, C, 2, net->cus, st);
+    if (e == 0) e = launch_dw(net->dw_down[i], ei, t2, n, 2, net->cus, st);
     x = act(p.X, i + 1, W[i + 1]);
     if (e == 0) e = launch_pw<EP_PLAIN>(net->pw_down[i], io, t2, x, none, n, C, st);
   }
@@ -563,7 +574,7 @@ extern "C" int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic
     const Act u = act(p.Y, i, W[i]);
     e = launch_pw<EP_DECONV>(net->up[i], io, x, u, act(p.e[i], i, W[i]), n, C, st);
     const Act t = act(p.T, i, W[i]);
-    if (e == 0) e = launch_dw<false>(net->dw_dec[i], io, zsig, u, t, n, C, 1, net->cus, st);
+    if (e == 0) e = launch_dw(net->dw_dec[i], u, t, n, 1, net->cus, st);
     x = act(p.X, i, W[i]);
     if (e == 0) e = launch_pw<EP_PLAIN>(net->pw_dec[i], io, t, x, none, n, C, st);
   }
