@@ -147,3 +147,23 @@ def test_split_layers_equal_one_pass(B):
     net.restore(bd, nd, outs=out, layers=(4, 10))
     torch.cuda.synchronize()
     assert torch.equal(out[0], whole)
+
+
+def test_errors_are_reported_before_any_launch(B):
+    layers = synth.cnn_layers(4, 1, seed=2)
+    net = B.Cnn(layers, 1)
+    basic, noisy = inputs(20, 30, 1, seed=1)
+    bd, nd = [torch.from_numpy(basic).cuda()], [torch.from_numpy(noisy).cuda()]
+    small = torch.empty(B.Cnn.workspace_bytes(1, 20, 30) - 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BM3DError):
+        net.restore(bd, nd, workspace=small)
+    ws = torch.empty(B.Cnn.workspace_bytes(1, 20, 30) + 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BM3DError):
+        net.restore(bd, nd, workspace=ws[1:])                  # misaligned
+    for rng_ in ((0, 5), (3, 3), (-1, 2)):
+        with pytest.raises(B.BM3DError):
+            net.restore(bd, nd, layers=rng_)
+    with pytest.raises(ValueError):
+        net.restore([torch.zeros((20, 30, 3), device="cuda")], [torch.zeros((20, 30, 3), dtype=torch.uint8,
+                                                                             device="cuda")])
+    torch.cuda.synchronize()

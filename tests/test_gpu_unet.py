@@ -120,3 +120,19 @@ def test_full_size_batch_sampled(B):
         assert np.isfinite(o).all()
     for i in (0, 15):
         check(outs[i], pairs[i][0], pairs[i][1], 25.0, weights, "512x512 image %d of 16" % i)
+
+
+def test_errors_are_reported_before_any_launch(B):
+    weights = synth.unet_net(1, seed=2)
+    net = B.Unet(weights, 1)
+    basic, noisy = inputs(20, 30, 1, seed=1)
+    bd, nd = [torch.from_numpy(basic).cuda()], [torch.from_numpy(noisy).cuda()]
+    need = net.workspace_bytes(1, 20, 30)
+    with pytest.raises(B.BM3DError):
+        net.restore(bd, nd, 25.0, workspace=torch.empty(need - 256, dtype=torch.uint8, device="cuda"))
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.BM3DError):
+        net.restore(bd, nd, 25.0, workspace=ws[16:])             # not 256-byte aligned
+    with pytest.raises(B.BM3DError):
+        net.restore(bd, nd, float("nan"))
+    torch.cuda.synchronize()
