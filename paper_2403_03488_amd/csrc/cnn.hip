@@ -56,10 +56,19 @@ constexpr int steps(int in) { return in == 0 ? 3 : 18; }
 constexpr int px_words(int in) { return in == 0 ? 1 : 8; }
 constexpr int data_words(int in, int nw, int pb) { return in == 0 ? halo_px(nw, pb) : halo_px(nw, pb) * 8; }
 constexpr int fetch_words(int in, int nw, int pb) { return (data_words(in, nw, pb) + 64 * nw - 1) / (64 * nw); }
+// The first layer's output tile is staged in LDS, 9 words per pixel (one of
+// padding), and written out row by row: 1 KB of consecutive bytes per store
+// instruction.  (Its contraction is short, so the stores dominate; the
+// 64 -> 64 layers store straight from the accumulators.)
+constexpr bool staged(int in) { return in == 0; }
+constexpr int stage_words(int nw, int pb) { return tile_rows(nw, pb) * kTW * 9; }
+constexpr int imax(int a, int b) { return a > b ? a : b; }
 // LDS: weight fragments, the per-channel scale and shift (2 x 64 floats),
-// the halo.
+// the halo (also the staging area once a staged tile is contracted).
 constexpr size_t lds_bytes(int in, int cob, int nw, int pb) {
-  return (size_t)(steps(in) * cob * 64 + 32 + halo_px(nw, pb) * px_words(in)) * 16;
+  return (size_t)(steps(in) * cob * 64 + 32 +
+                  imax(halo_px(nw, pb) * px_words(in), staged(in) ? stage_words(nw, pb) : 0)) *
+         16;
 }
 
 struct Io {
@@ -211,13 +220,14 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
 
     const int img = t / s.per_img, r = t - img * s.per_img;
     const int ty = r / s.tiles_x, tx = r - ty * s.tiles_x;
+    if constexpr (staged(IN)) {
+      // affine + ReLU + bf16 into the staging area (the halo is dead once
+      // every wave is done with it), then whole pixel rows out
+      __syncthreads();
+      char* stg = (char*)sh;
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const int gy = ty * TR + wv * (PB / 2) + (pb >> 1), gx = tx * kTW + (pb & 1) * 16 + (l & 15);
-      if (gy >= s.h || gx >= s.w) continue;
-      const size_t pix = (size_t)gy * s.w + gx;
-      if constexpr (!LAST) {
-        __bf16* dst = act_out + ((size_t)img * s.h * s.w + pix) * kF + 4 * (l >> 4);
+      for (int pb = 0; pb < PB; ++pb) {
+        const int q = (wv * (PB / 2) + (pb >> 1)) * kTW + (pb & 1) * 16 + (l & 15);
 #pragma unroll
         for (int cb = 0; cb < COB; ++cb) {
           // channels cb * 16 + 4 (l / 16) + i
@@ -226,16 +236,47 @@ __global__ void __launch_bounds__(64 * NW) k_conv(LayerDev L, Io io, const __bf1
           f32x4 v;
 #pragma unroll
           for (int i = 0; i < 4; ++i) v[i] = fmaxf(fmaf(acc[cb][pb][i], sc[i], sf[i]), 0.f);
-          const bf16x4 o = __builtin_convertvector(v, bf16x4);
-          *(u32x2*)(dst + cb * 16) = __builtin_bit_cast(u32x2, o);
+          *(u32x2*)(stg + q * 144 + cb * 32 + (l >> 4) * 8) =
+              __builtin_bit_cast(u32x2, __builtin_convertvector(v, bf16x4));
         }
-      } else {
-        const float* bsc = io.basic[img] + pix * s.c;
-        float* o = io.out[img] + pix * s.c;
+      }
+      __syncthreads();
+      constexpr int OW = TR * kTW * 8;  // output words of a tile
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int co = 4 * (l >> 4) + i;
-          if (co < s.c) o[co] = bsc[co] + 255.f * fmaf(acc[0][pb][i], saff[co], saff[kF + co]);
+      for (int k = 0; k < (OW + NT - 1) / NT; ++k) {
+        const int wd = tid + k * NT;
+        const int q = wd >> 3, j = wd & 7;
+        const int gy = ty * TR + q / kTW, gx = tx * kTW + q % kTW;
+        if (wd < OW && gy < s.h && gx < s.w)
+          *(u32x4*)(act_out + ((size_t)img * s.h * s.w + (size_t)gy * s.w + gx) * kF + j * 8) = sh[q * 9 + j];
+      }
+    } else {
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        const int gy = ty * TR + wv * (PB / 2) + (pb >> 1), gx = tx * kTW + (pb & 1) * 16 + (l & 15);
+        if (gy >= s.h || gx >= s.w) continue;
+        const size_t pix = (size_t)gy * s.w + gx;
+        if constexpr (!LAST) {
+          __bf16* dst = act_out + ((size_t)img * s.h * s.w + pix) * kF + 4 * (l >> 4);
+#pragma unroll
+          for (int cb = 0; cb < COB; ++cb) {
+            // channels cb * 16 + 4 (l / 16) + i
+            const f32x4 sc = *(const f32x4*)(saff + cb * 16 + 4 * (l >> 4));
+            const f32x4 sf = *(const f32x4*)(saff + kF + cb * 16 + 4 * (l >> 4));
+            f32x4 v;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = fmaxf(fmaf(acc[cb][pb][i], sc[i], sf[i]), 0.f);
+            const bf16x4 o = __builtin_convertvector(v, bf16x4);
+            *(u32x2*)(dst + cb * 16) = __builtin_bit_cast(u32x2, o);
+          }
+        } else {
+          const float* bsc = io.basic[img] + pix * s.c;
+          float* o = io.out[img] + pix * s.c;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int co = 4 * (l >> 4) + i;
+            if (co < s.c) o[co] = bsc[co] + 255.f * fmaf(acc[0][pb][i], saff[co], saff[kF + co]);
+          }
         }
       }
     }
