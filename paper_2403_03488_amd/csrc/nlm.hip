@@ -16,7 +16,7 @@
 // pixels in LDS.  Lane l stands for image column x0 - f + l.  Per search
 // offset, for each of the kRows + 2f rows it forms the squared difference of
 // its column (its reference samples stay in registers), adds those of lanes
-// l + 1 .. l + 2f through cross-lane permutes (the horizontal patch sums, so
+// l + 1 .. l + 2f through whole-wave DPP shifts (the horizontal patch sums, so
 // lanes 0 .. 63 - 2f hold outputs), sums 2f + 1 of those rows per output
 // row, and updates each output's sums with one exponential.  E_min is
 // tracked on line: a candidate below the running minimum rescales the sums
@@ -56,8 +56,9 @@ __device__ inline int reflect(int t, int n) {
   return t < n ? t : p - 1 - t;
 }
 
-__device__ inline float lane_down(float v, int addr) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+// Lane l takes lane l + 1's value (a DPP whole-wave shift); lane 63 gets 0.
+__device__ inline float wave_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
 template <int C, int F>
@@ -87,9 +88,6 @@ __global__ void __launch_bounds__(64) k_nlm(Batch bt, int H, int W, float two_si
   for (int c = 0; c < C; c++)
 #pragma unroll
     for (int rr = 0; rr < NR; rr++) ref[c][rr] = U[c * plane + (r + rr) * RP + r + l];
-  int addr[2 * F + 1];
-#pragma unroll
-  for (int t = 1; t <= 2 * F; t++) addr[t] = ((l + t) & 63) << 2;
   const int X = x0 + l;                       // output column of lane l
   const bool lane_out = l < out_cols(F) && X < W;
   float num[C][kRows], den[kRows], mn[kRows];
@@ -114,9 +112,14 @@ __global__ void __launch_bounds__(64) k_nlm(Batch bt, int H, int W, float two_si
           const float e = ref[c][rr] - U[c * plane + cand + rr * RP];
           d = __builtin_fmaf(e, e, d);
         }
-        float hsum = d;
+        // lanes l + 1 .. l + 2f by whole-wave shifts of one lane (the top
+        // lanes, which hold no output, read zero)
+        float hsum = d, sh = d;
 #pragma unroll
-        for (int t = 1; t <= 2 * F; t++) hsum += lane_down(d, addr[t]);
+        for (int t = 1; t <= 2 * F; t++) {
+          sh = wave_next(sh);
+          hsum += sh;
+        }
         hs[rr] = hsum;
       }
       const bool colok = lane_out && X + dx >= 0 && X + dx < W;
