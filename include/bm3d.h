@@ -252,10 +252,10 @@ int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basic, const ui
  * DS(ci -> co, s) = depthwise 3x3 (stride s, zero padding 1) + affine + ReLU,
  * then pointwise ci -> co + affine + ReLU; "affine" is an optional bias then
  * an optional inference-mode batch normalisation.  Default widths
- * w = (32, 64, 128, 256, 256).  Pointwise, deconvolution and output weights
- * are rounded to bfloat16 and contracted on the matrix cores with FP32
- * accumulation; depthwise kernels stay FP32; activations are stored in
- * bfloat16; the output is FP32. */
+ * w = (32, 64, 128, 256, 256).  Pointwise and deconvolution weights are
+ * rounded to bfloat16 and contracted on the matrix cores with FP32
+ * accumulation; depthwise and output-layer weights stay FP32; activations
+ * are stored in bfloat16; the output is FP32. */
 typedef struct {
   const float* dw;       /* host [ci][3][3], required */
   const float* dw_bias;  /* host [ci] or NULL */

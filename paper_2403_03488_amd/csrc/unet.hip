@@ -6,18 +6,20 @@
 //   x_hat = first-stage estimate + 255 F(z).
 //
 // Activations are NHWC bfloat16, each pixel a whole number of 16-byte words
-// (8 channels).  Two kernels carry the network:
+// (8 channels).  These kernels carry the network:
 //   k_pack  z as one bfloat16 word per pixel (2C + 1 <= 7 channels + zero).
 //   k_dw  depthwise 3x3 (stride 1 or 2, zero padding) + per-channel affine +
 //         ReLU on the vector ALUs, one thread per output word.
-//   k_pw  every 1x1 product on the bf16 matrix cores
+//   k_pw  every 1x1 product but the last on the bf16 matrix cores
 //         (v_mfma_f32_16x16x32_bf16, FP32 accumulation): output columns are
 //         the rows of the product and pixels its columns, a lane's 8
 //         contraction slots are one 16-byte word of an input pixel.  Its
-//         epilogue is the pointwise layer (affine + ReLU), the 2x2
+//         epilogue is the pointwise layer (affine + ReLU) or the 2x2
 //         deconvolution (the product has 4 x co columns, one per output
-//         sub-pixel; bias + ReLU, crop, + skip), or the output layer
-//         (+ bias, x 255, + first-stage estimate, FP32).
+//         sub-pixel; bias + ReLU, crop, + skip).
+//   k_out the output layer w_0 -> C (at most 3 columns: one pixel per
+//         thread on the vector ALUs, FP32) + bias, x 255, + the first-stage
+//         estimate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -56,6 +58,11 @@ struct Act {
 struct DwDev {
   const float* w;    // [cw * 8][9]
   const float* aff;  // scale [cw * 8], shift [cw * 8]
+};
+
+struct OutDev {
+  const float* w;  // [C][w_0]
+  const float* b;  // [C]
 };
 
 struct PwDev {
@@ -128,7 +135,7 @@ __global__ void __launch_bounds__(kDwThreads) k_dw(DwDev L, Act in, Act out, int
 }
 
 // ------------------------------------------------------------- pointwise ---
-enum { EP_PLAIN = 0, EP_DECONV = 1, EP_FINAL = 2 };
+enum { EP_PLAIN = 0, EP_DECONV = 1 };
 
 // grid: x = 256-pixel tiles of the input, y = groups of 64 output columns.
 template <int EP>
@@ -199,18 +206,38 @@ __global__ void __launch_bounds__(kPwThreads) k_pw(PwDev L, Io io, Act in, Act o
         for (int i = 0; i < 4; ++i)
           v[i] = fmaxf(fmaf(acc[cb][pb][i], sc[i], sf[i]), 0.f) + (float)sk[i];
         *(u32x2*)(out.p + q) = __builtin_bit_cast(u32x2, __builtin_convertvector(v, bf16x4));
-      } else {
-        const int img = (int)(p / ((long long)in.h * in.w));
-        const int r = (int)(p - (long long)img * in.h * in.w);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int ch = nn + i;
-          if (ch < C) {
-            const size_t q = (size_t)r * C + ch;
-            io.out[img][q] = io.basic[img][q] + 255.f * fmaf(acc[cb][pb][i], sc[i], sf[i]);
-          }
-        }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- output ---
+__global__ void __launch_bounds__(kDwThreads) k_out(OutDev L, Io io, Act in, int n, int C) {
+  __shared__ float sw[3 * kMaxWidth + 3];
+  const int cp = in.cw * 8;
+  for (int i = threadIdx.x; i < C * cp; i += kDwThreads) sw[i] = L.w[i];
+  if (threadIdx.x < C) sw[C * cp + threadIdx.x] = L.b[threadIdx.x];
+  __syncthreads();
+  const long long total = (long long)n * in.h * in.w;
+  for (long long p = (long long)blockIdx.x * kDwThreads + threadIdx.x; p < total;
+       p += (long long)gridDim.x * kDwThreads) {
+    const int img = (int)(p / ((long long)in.h * in.w));
+    const size_t r = (size_t)(p - (long long)img * in.h * in.w);
+    float acc[3] = {0.f, 0.f, 0.f};
+    for (int j = 0; j < in.cw; ++j) {
+      const bf16x8 v = __builtin_bit_cast(bf16x8, *(const u32x4*)(in.p + (size_t)p * cp + j * 8));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (c >= C) break;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[c] = fmaf(sw[c * cp + j * 8 + e], (float)v[e], acc[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c >= C) break;
+      const size_t q = r * C + c;
+      io.out[img][q] = io.basic[img][q] + 255.f * (acc[c] + sw[C * cp + c]);
     }
   }
 }
@@ -233,7 +260,8 @@ struct bm3d_unet {
   int widths[5] = {};
   void* mem = nullptr;
   DwDev dw_enc[4], dw_down[4], dw_dec[4];
-  PwDev pw_enc[4], pw_down[4], pw_dec[4], up[4], out;
+  PwDev pw_enc[4], pw_down[4], pw_dec[4], up[4];
+  OutDev out;
 };
 
 namespace {
@@ -374,7 +402,7 @@ extern "C" int bm3d_unet_create(int c, const int* widths, const bm3d_unet_weight
 
   Packer pk;
   DwOff de[4], dd[4], dc[4];
-  PwOff pe[4], pd[4], pc[4], pu[4], po;
+  PwOff pe[4], pd[4], pc[4], pu[4];
   for (int i = 0; i < 4; ++i) {
     const int ci = i == 0 ? cin : W[i];
     de[i] = pack_dw(pk, wts->enc[i], ci);
@@ -398,12 +426,11 @@ extern "C" int bm3d_unet_create(int c, const int* widths, const bm3d_unet_weight
           *sf = ub ? ub[col % co2] : 0.f;
         });
   }
-  po = pack_pw(
-      pk, W[0], c, c, [&](int col, int i) { return wts->out_weight[(size_t)col * W[0] + i]; },
-      [&](int col, float* sc, float* sf) {
-        *sc = 1.f;
-        *sf = wts->out_bias ? wts->out_bias[col] : 0.f;
-      });
+  // output layer: FP32 [c][w_0] and bias [c]
+  std::vector<float> ow((size_t)c * W[0] + c, 0.f);
+  for (size_t i = 0; i < (size_t)c * W[0]; ++i) ow[i] = wts->out_weight[i];
+  for (int i = 0; i < c; ++i) ow[(size_t)c * W[0] + i] = wts->out_bias ? wts->out_bias[i] : 0.f;
+  const size_t oo = pk.put(ow.data(), ow.size() * 4);
 
   bm3d_unet* n = new (std::nothrow) bm3d_unet;
   if (!n) return BM3D_ERR_NOMEM;
@@ -436,7 +463,7 @@ extern "C" int bm3d_unet_create(int c, const int* widths, const bm3d_unet_weight
     n->pw_dec[i] = pv(pc[i]);
     n->up[i] = pv(pu[i]);
   }
-  n->out = pv(po);
+  n->out = OutDev{(const float*)(base + oo), (const float*)(base + oo) + (size_t)c * W[0]};
   n->c = c;
   for (int i = 0; i < 5; ++i) n->widths[i] = W[i];
   *net = n;
@@ -578,6 +605,10 @@ extern "C" int bm3d_unet_restore(const bm3d_unet* net, const float* const* basic
     x = act(p.X, i, W[i]);
     if (e == 0) e = launch_pw<EP_PLAIN>(net->pw_dec[i], io, t, x, none, n, C, st);
   }
-  if (e == 0) e = launch_pw<EP_FINAL>(net->out, io, x, none, none, n, C, st);
+  if (e == 0) {
+    hipLaunchKernelGGL(k_out, dim3(grid_of((long long)n * h * w, net->cus)), dim3(kDwThreads), 0, st, net->out, io, x,
+                       n, C);
+    e = hipGetLastError() == hipSuccess ? 0 : -1;
+  }
   return e == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
