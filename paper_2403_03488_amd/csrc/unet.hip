@@ -8,8 +8,9 @@
 // Activations are NHWC bfloat16, each pixel a whole number of 16-byte words
 // (8 channels).  These kernels carry the network:
 //   k_pack  z as one bfloat16 word per pixel (2C + 1 <= 7 channels + zero).
-//   k_dw  depthwise 3x3 (stride 1 or 2, zero padding) + per-channel affine +
-//         ReLU on the vector ALUs, one thread per output word.
+//   k_dw  depthwise 3x3 (stride 2, zero padding) + per-channel affine +
+//         ReLU on the vector ALUs, one thread per output word; k_dw2 the
+//         same at stride 1, two vertically adjacent outputs per thread.
 //   k_pw  every 1x1 product but the last on the bf16 matrix cores
 //         (v_mfma_f32_16x16x32_bf16, FP32 accumulation): output columns are
 //         the rows of the product and pixels its columns, a lane's 8
@@ -131,6 +132,55 @@ __global__ void __launch_bounds__(kDwThreads) k_dw(DwDev L, Act in, Act out, int
 #pragma unroll
     for (int e = 0; e < 8; ++e) o[e] = (__bf16)fmaxf(fmaf(acc[e], saf[j * 8 + e], saf[cp + j * 8 + e]), 0.f);
     *(u32x4*)(out.p + (size_t)pix * cp + j * 8) = __builtin_bit_cast(u32x4, o);
+  }
+}
+
+// Stride 1, two vertically adjacent outputs per thread: their 3x3
+// neighbourhoods share two input rows, 12 word loads instead of 18.
+__global__ void __launch_bounds__(kDwThreads) k_dw2(DwDev L, Act in, Act out, int n) {
+  __shared__ float sw[kMaxWidth * 9];
+  __shared__ float saf[2 * kMaxWidth];
+  const int cp = out.cw * 8;
+  for (int i = threadIdx.x; i < cp * 9; i += kDwThreads) sw[i] = L.w[i];
+  for (int i = threadIdx.x; i < 2 * cp; i += kDwThreads) saf[i] = L.aff[i];
+  __syncthreads();
+  const int hp = (out.h + 1) / 2;  // row pairs
+  const long long total = (long long)n * hp * out.w * out.cw;
+  for (long long idx = (long long)blockIdx.x * kDwThreads + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * kDwThreads) {
+    const int j = (int)(idx % out.cw);
+    const long long pp = idx / out.cw;
+    const int img = (int)(pp / ((long long)hp * out.w));
+    const int r = (int)(pp - (long long)img * hp * out.w);
+    const int oy = 2 * (r / out.w), ox = r - (r / out.w) * out.w;
+    float a0[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, a1[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ry = 0; ry < 4; ++ry) {  // input rows oy - 1 .. oy + 2
+      const int iy = oy - 1 + ry;
+      if (iy < 0 || iy >= in.h) continue;
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        const int ix = ox + tx - 1;
+        if (ix < 0 || ix >= in.w) continue;
+        const bf16x8 bv = __builtin_bit_cast(
+            bf16x8, *(const u32x4*)(in.p + (((size_t)img * in.h + iy) * in.w + ix) * (in.cw * 8) + j * 8));
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float x = (float)bv[e];
+          if (ry <= 2) a0[e] = fmaf(sw[(j * 8 + e) * 9 + ry * 3 + tx], x, a0[e]);
+          if (ry >= 1) a1[e] = fmaf(sw[(j * 8 + e) * 9 + (ry - 1) * 3 + tx], x, a1[e]);
+        }
+      }
+    }
+    bf16x8 o0, o1;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      o0[e] = (__bf16)fmaxf(fmaf(a0[e], saf[j * 8 + e], saf[cp + j * 8 + e]), 0.f);
+      o1[e] = (__bf16)fmaxf(fmaf(a1[e], saf[j * 8 + e], saf[cp + j * 8 + e]), 0.f);
+    }
+    const size_t base = ((size_t)img * out.h + oy) * out.w + ox;
+    *(u32x4*)(out.p + base * cp + j * 8) = __builtin_bit_cast(u32x4, o0);
+    if (oy + 1 < out.h) *(u32x4*)(out.p + (base + out.w) * cp + j * 8) = __builtin_bit_cast(u32x4, o1);
   }
 }
 
@@ -529,8 +579,12 @@ int launch_pack(const Io& io, float zsig, Act out, int n, int C, int cus, hipStr
 }
 
 int launch_dw(const DwDev& L, Act in, Act out, int n, int stride, int cus, hipStream_t st) {
-  hipLaunchKernelGGL(k_dw, dim3(grid_of((long long)n * out.h * out.w * out.cw, cus)), dim3(kDwThreads), 0, st, L,
-                     in, out, n, stride);
+  if (stride == 1)
+    hipLaunchKernelGGL(k_dw2, dim3(grid_of((long long)n * ((out.h + 1) / 2) * out.w * out.cw, cus)),
+                       dim3(kDwThreads), 0, st, L, in, out, n);
+  else
+    hipLaunchKernelGGL(k_dw, dim3(grid_of((long long)n * out.h * out.w * out.cw, cus)), dim3(kDwThreads), 0, st, L,
+                       in, out, n, stride);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
