@@ -308,6 +308,9 @@ static int launch(const LayerDev& L, const Io& io, const __bf16* in, __bf16* out
 
 // Waves and 16-pixel blocks per wave of every layer kind.
 constexpr int kNw = 8, kPb = 4;
+// The last layer (4 MFMAs per 5 fragment reads a step) takes 8-row tiles
+// of 2 blocks per wave: two workgroups, 16 waves, per CU.
+constexpr int kPbLast = 2;
 
 static uint16_t bf16_bits(float x) {
   uint32_t u;
@@ -457,8 +460,10 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
     io.out[i] = out[i];
   }
   const long long tx = (w + kTW - 1) / kTW, ty = (h + tile_rows(kNw, kPb) - 1) / tile_rows(kNw, kPb);
-  if (tx * ty * n >= (1ll << 31) || (long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
+  const long long tyl = (h + tile_rows(kNw, kPbLast) - 1) / tile_rows(kNw, kPbLast);
+  if (tx * tyl * n >= (1ll << 31) || (long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
   const Shape s{n, h, w, net->c, (int)tx, (int)(tx * ty), (int)(tx * ty * n)};
+  const Shape sl{n, h, w, net->c, (int)tx, (int)(tx * tyl), (int)(tx * tyl * n)};
   size_t need = 0;
   (void)bm3d_cnn_workspace_bytes(n, h, w, &need);
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 15)) return BM3D_ERR_WORKSPACE;
@@ -475,7 +480,7 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
     else if (k < K - 1)
       e = launch<1, 4, false, kNw, kPb, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s, net->cus, st);
     else
-      e = launch<1, 1, true, kNw, kPb, true>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, s, net->cus, st);
+      e = launch<1, 1, true, kNw, kPbLast, true>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, sl, net->cus, st);
   }
   return e == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
