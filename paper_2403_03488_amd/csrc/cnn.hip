@@ -476,7 +476,7 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
   int e = 0;
   for (int k = first; k < last && e == 0; ++k) {
     if (k == 0)
-      e = launch<0, 4, false, kNw, kPb, true>(net->L[0], io, nullptr, act[0], s, net->cus, st);
+      e = launch<0, 4, false, kNw, kPbLast, true>(net->L[0], io, nullptr, act[0], sl, net->cus, st);
     else if (k < K - 1)
       e = launch<1, 4, false, kNw, kPb, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s, net->cus, st);
     else
