@@ -11,11 +11,15 @@
 // contraction slots are 8 consecutive channels of one pixel at one tap, i.e.
 // one 16-byte word of an NHWC activation.
 //
-// A workgroup (8 waves) is persistent: it copies the layer's weights, already
-// laid out on the host in fragment order, into LDS once and then walks 16x32
-// pixel output tiles.  A tile's 18x34 input halo sits in LDS with its 16-byte
-// words XOR-swizzled by pixel (conflict-free fragment reads); the next tile's
-// halo is fetched into registers while the current one is contracted.  Bias
+// Workgroups are persistent: each copies the layer's weights, already laid
+// out on the host in fragment order, into LDS once and then walks output
+// tiles (16x32 pixels for the 64 -> 64 layers, one 16-wave workgroup per CU;
+// 8x32 for the thin first and last layers, two 8-wave workgroups per CU);
+// every wave computes 32 pixels.  A tile's input halo sits in LDS with its
+// 16-byte words XOR-swizzled by pixel (conflict-free fragment reads); the
+// next tile's halo is fetched into registers while the current one is
+// contracted.  The first layer stages its output tile in LDS and writes
+// whole pixel rows.  Bias
 // and batch normalisation are one per-channel affine map in the epilogue
 // (FP32), followed by ReLU and a round-to-nearest bf16 store; the last layer
 // adds 255 F to the first-stage estimate and writes FP32.
@@ -307,10 +311,12 @@ static int launch(const LayerDev& L, const Io& io, const __bf16* in, __bf16* out
 }
 
 // Waves and 16-pixel blocks per wave of every layer kind.
-constexpr int kNw = 8, kPb = 4;
-// The last layer (4 MFMAs per 5 fragment reads a step) takes 8-row tiles
-// of 2 blocks per wave: two workgroups, 16 waves, per CU.
-constexpr int kPbLast = 2;
+// Every kind runs 16 waves per CU, each of 2 blocks (32 pixels): the
+// 64 -> 64 layers as one workgroup of 16 waves on 16 x 32 tiles (its LDS
+// holds one), the thin first and last layers as two workgroups of 8 waves
+// on 8 x 32 tiles.  More waves hide more fragment-read latency, which pays
+// for the extra reads of the narrower wave tile.
+constexpr int kNwHidden = 16, kNw = 8, kPb = 2;
 
 static uint16_t bf16_bits(float x) {
   uint32_t u;
@@ -459,11 +465,12 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
     io.noisy[i] = noisy[i];
     io.out[i] = out[i];
   }
-  const long long tx = (w + kTW - 1) / kTW, ty = (h + tile_rows(kNw, kPb) - 1) / tile_rows(kNw, kPb);
-  const long long tyl = (h + tile_rows(kNw, kPbLast) - 1) / tile_rows(kNw, kPbLast);
+  const long long tx = (w + kTW - 1) / kTW;
+  const long long ty = (h + tile_rows(kNwHidden, kPb) - 1) / tile_rows(kNwHidden, kPb);
+  const long long tyl = (h + tile_rows(kNw, kPb) - 1) / tile_rows(kNw, kPb);
   if (tx * tyl * n >= (1ll << 31) || (long long)h * w >= (1ll << 31)) return BM3D_ERR_UNSUPPORTED;
-  const Shape s{n, h, w, net->c, (int)tx, (int)(tx * ty), (int)(tx * ty * n)};
-  const Shape sl{n, h, w, net->c, (int)tx, (int)(tx * tyl), (int)(tx * tyl * n)};
+  const Shape s{n, h, w, net->c, (int)tx, (int)(tx * ty), (int)(tx * ty * n)};      // 64 -> 64 layers
+  const Shape sl{n, h, w, net->c, (int)tx, (int)(tx * tyl), (int)(tx * tyl * n)};   // first and last
   size_t need = 0;
   (void)bm3d_cnn_workspace_bytes(n, h, w, &need);
   if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 15)) return BM3D_ERR_WORKSPACE;
@@ -476,11 +483,11 @@ extern "C" int bm3d_cnn_run_layers(const bm3d_cnn* net, const float* const* basi
   int e = 0;
   for (int k = first; k < last && e == 0; ++k) {
     if (k == 0)
-      e = launch<0, 4, false, kNw, kPbLast, true>(net->L[0], io, nullptr, act[0], sl, net->cus, st);
+      e = launch<0, 4, false, kNw, kPb, true>(net->L[0], io, nullptr, act[0], sl, net->cus, st);
     else if (k < K - 1)
-      e = launch<1, 4, false, kNw, kPb, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s, net->cus, st);
+      e = launch<1, 4, false, kNwHidden, kPb, true>(net->L[k], io, act[(k - 1) & 1], act[k & 1], s, net->cus, st);
     else
-      e = launch<1, 1, true, kNw, kPbLast, true>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, sl, net->cus, st);
+      e = launch<1, 1, true, kNw, kPb, true>(net->L[K - 1], io, act[(K - 2) & 1], nullptr, sl, net->cus, st);
   }
   return e == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
