@@ -805,9 +805,9 @@ def main():
     c1 = torch.empty(R, dtype=torch.int32, device="cuda")
     i2 = torch.empty((R, p.n_wie), dtype=torch.int32, device="cuda")
     c2 = torch.empty(R, dtype=torch.int32, device="cuda")
-    num = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
+    num = torch.empty((1, H, W), dtype=torch.int64, device="cuda")
     wsum = torch.empty_like(num)
-    basic = torch.empty_like(num)
+    basic = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
     for im in imgs:
         bm3d.prepare(im, planar, lum)
         bm3d.block_match(lum, 1, p, i1, c1)

@@ -67,13 +67,17 @@ typedef enum {
  * bm3d_params_default (sigma <= 40: 2500/400, else 5000/3500) instead of the
  * params' values -- for batches and request streams with mixed noise levels */
 #define BM3D_FLAG_SIGMA_PROFILE 2u
+/* testing aid: the workspace (and every image of a batched plan) gets a
+ * BM3D_BUF_NKEPT region that step-1 filtering fills with each group's
+ * number of kept coefficients */
+#define BM3D_FLAG_DEBUG_NKEPT 4u
 
 typedef struct {
   int search_ht, search_wie; /* S of each step, 1..32 */
   int n_ht, n_wie;           /* max group sizes, powers of two in 1..32 */
   float lambda_ht;           /* step-1 hard threshold multiplier; keep |c| > lambda*sigma */
   float tau_ht, tau_wie;     /* a candidate joins only if SSD <= 64*tau (INFINITY: no limit) */
-  float kaiser_beta;         /* Kaiser window parameter of the aggregation (2.0) */
+  float kaiser_beta;         /* Kaiser window parameter of the aggregation, 0..50 (2.0) */
   int xform;                 /* bm3d_xform */
   int tile_refs;             /* references per side of the tile one wavefront filters and
                                 aggregates (0 = auto); limited by the LDS budget */
@@ -86,6 +90,34 @@ typedef struct {
   size_t workspace_bytes;
 } bm3d_params;
 
+/* Aggregation accumulators.  num and wsum are signed 64-bit fixed point
+ * (value = integer / 2^BM3D_NUM_FRAC_BITS, resp. 2^BM3D_WSUM_FRAC_BITS).
+ * Every addition into them is an exact integer addition, so their sums, and
+ * everything computed from them, do not depend on the order in which work
+ * items add: a given input and params give the same output bit for bit,
+ * whatever the stream, batch, launch shape or scheduling.  To keep every sum
+ * in range the step-2 group weight 1/sum W^2 is capped at 2^10 (a group
+ * whose pilot spectrum is all but zero filters to ~0 whatever its weight). */
+#define BM3D_NUM_FRAC_BITS 28
+#define BM3D_WSUM_FRAC_BITS 40
+
+/* The per-image working buffers inside a workspace (bm3d_workspace_buffer)
+ * or a batched plan (bm3d_batch_copy_buffer). */
+typedef enum {
+  BM3D_BUF_PLANAR = 0, /* float [c][h][w] working channels (grey / opponent) */
+  BM3D_BUF_LUM8 = 1,   /* uint8 [h][w] step-1 matching luminance */
+  BM3D_BUF_LUMF = 2,   /* float [h][w] step-2 matching luminance */
+  BM3D_BUF_BASIC = 3,  /* float [c][h][w] basic estimate (step 1 output) */
+  BM3D_BUF_NUM = 4,    /* int64 [c][h][w] aggregation numerator (fixed point) */
+  BM3D_BUF_WSUM = 5,   /* int64 [c][h][w] group weights per patch corner (fixed point) */
+  BM3D_BUF_IDX1 = 6,   /* int32 [R][n_ht] step-1 groups */
+  BM3D_BUF_CNT1 = 7,   /* int32 [R] step-1 group sizes */
+  BM3D_BUF_IDX2 = 8,   /* int32 [R][n_wie] step-2 groups */
+  BM3D_BUF_CNT2 = 9,   /* int32 [R] step-2 group sizes */
+  BM3D_BUF_NKEPT = 10, /* int32 [c][R] step-1 kept counts (BM3D_FLAG_DEBUG_NKEPT only; else 0 bytes) */
+  BM3D_NUM_BUFFERS = 11
+} bm3d_buffer;
+
 /* Defaults for noise level sigma: S=32 both steps, n 16/32, lambda 2.7,
  * beta 2.0, FP32 transforms, tau 2500/400 (sigma <= 40) or 5000/3500. */
 int bm3d_params_default(float sigma, bm3d_params* p);
@@ -93,58 +125,82 @@ int bm3d_params_default(float sigma, bm3d_params* p);
 /* Number of reference patches of an h x w image (rows x cols of the grid). */
 int bm3d_num_refs(int h, int w);
 
-/* Device bytes bm3d_denoise needs in params->workspace for this image. */
+/* Device bytes bm3d_denoise needs in params->workspace for this image
+ * (0 if the arguments are invalid). */
 size_t bm3d_workspace_size(int h, int w, int c, const bm3d_params* p);
 
-/* Colour/format preparation.  img: HWC uint8 [h][w][c].  planar: float
- * [c][h][w] -- the grey values (c=1) or the orthonormal opponent channels
- * (1,1,1)/sqrt3, (1,0,-1)/sqrt2, (1,-2,1)/sqrt6 (c=3).  lum: uint8 [h][w]
- * step-1 matching luminance -- the grey value or round((R+G+B)/3). */
+/* Where bm3d_denoise keeps one working buffer inside its workspace: byte
+ * offset from the workspace start (256-byte aligned) and size.  Host only;
+ * BM3D_ERR_ARG for an unknown buffer or a null output. */
+int bm3d_workspace_buffer(int h, int w, int c, const bm3d_params* p, int buffer, size_t* offset,
+                          size_t* bytes);
+
+/* Colour/format preparation (colour images follow the CBM3D variant cited
+ * in Table 1: an opponent colour transform, grouping on luminance).
+ * img: HWC uint8 [h][w][c].  planar: float [c][h][w] -- the grey values
+ * (c=1) or the orthonormal opponent channels (1,1,1)/sqrt3, (1,0,-1)/sqrt2,
+ * (1,-2,1)/sqrt6 (c=3).  lum: uint8 [h][w] step-1 matching luminance -- the
+ * grey value or round((R+G+B)/3).  All device pointers, caller-owned. */
 int bm3d_prepare(const uint8_t* img, int h, int w, int c, float* planar, uint8_t* lum,
                  bm3d_stream_t stream);
 
-/* Grouping by block matching (one step).  step 1: src is uint8 [h][w]
- * (src_is_f32 = 0), distances are exact integer SSDs computed as
- * |p|^2 + |q|^2 - 2 p.q on int8 matrix cores (values shifted by -128).
- * step 2: src is float [h][w] (src_is_f32 = 1), FP32 SSDs.  For every
- * reference r (row-major over the grid) the group is r followed by the
- * other window candidates with SSD <= 64*tau in increasing (SSD, index)
- * order, truncated to n = the largest power of two <= min(1 + #passing,
- * n_max), n_max = n_ht or n_wie.  idx: int32 [R][n_max], unused slots -1;
- * cnt: int32 [R] = n. */
+/* Grouping by block matching (one step): the grouping of the BM3D first
+ * stage of Fig. 1 (Section II).  step 1: src is uint8 [h][w] (src_is_f32 = 0),
+ * distances are exact integer SSDs computed as |p|^2 + |q|^2 - 2 p.q on
+ * int8 matrix cores (values shifted by -128).  step 2: src is float [h][w]
+ * (src_is_f32 = 1), FP32 SSDs.  For every reference r (row-major over the
+ * grid) the group is r followed by the other window candidates with
+ * SSD <= 64*tau in increasing (SSD, index) order, truncated to n = the
+ * largest power of two <= min(1 + #passing, n_max), n_max = n_ht or n_wie.
+ * idx: device int32 [R][n_max], unused slots -1; cnt: device int32 [R] = n.
+ * Invalid sizes, params or step/src_is_f32 pairs: BM3D_ERR_ARG, nothing
+ * enqueued. */
 int bm3d_block_match(const void* src, int src_is_f32, int h, int w, int step,
                      const bm3d_params* p, int32_t* idx, int32_t* cnt, bm3d_stream_t stream);
 
-/* Collaborative filtering of all groups, accumulated (+=) into num/wsum
- * (planar float [c][h][w]).  noisy: planar working channels.  step 1: 3D
- * spectrum hard-thresholded at lambda*sigma (kept iff |s| > lambda*sigma),
+/* Collaborative filtering of all groups (the 3-D transform shrinkage of the
+ * BM3D first stage of Fig. 1, Section II), accumulated (+=) into num/wsum,
+ * device int64 fixed point [c][h][w] (BM3D_NUM_FRAC_BITS, BM3D_WSUM_FRAC_BITS).  noisy: device
+ * float planar working channels; idx/cnt as from bm3d_block_match.  step 1:
+ * 3-D spectrum hard-thresholded at lambda*sigma (kept iff |s| > lambda*sigma),
  * group weight 1/N_kept (1 if none kept); basic must be NULL.  step 2:
  * empirical Wiener shrinkage W = B^2/(B^2+sigma^2) of the noisy spectrum, B
- * the spectrum of `basic` (planar) over the same patches, weight 1/sum W^2
- * (1 if 0).  Weights are per channel; each filtered patch at top-left
- * (y0, x0) adds w*K(u)*K(v)*value into num[y0+u][x0+v] (K = Kaiser window of
- * p->kaiser_beta) and w into wsum[y0][x0].  The aggregation denominator of
- * the method, sum of w*K(u)*K(v) over the patches covering a pixel, is wsum
- * correlated with the 8x8 Kaiser window; bm3d_aggregate forms it. */
+ * the spectrum of `basic` (device planar float) over the same patches, weight
+ * 1/max(sum W^2, 2^-10).  Weights are per channel.  Each filtered patch at
+ * top-left (y0, x0) adds w*K(u)*K(v)*value into num[y0+u][x0+v] (K = Kaiser
+ * window of p->kaiser_beta) and w into wsum[y0][x0].
+ * Departure from a per-pixel denominator output: the method's aggregation
+ * denominator, the sum of w*K(u)*K(v) over the patches covering a pixel, is
+ * the same sum regrouped as wsum correlated with the 8x8 Kaiser window;
+ * bm3d_aggregate forms it, so the filter writes one weight per patch
+ * instead of 64. */
 int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int c,
                        float sigma, int step, const int32_t* idx, const int32_t* cnt,
-                       const bm3d_params* p, float* num, float* wsum, bm3d_stream_t stream);
+                       const bm3d_params* p, int64_t* num, int64_t* wsum, bm3d_stream_t stream);
 
-/* out = num/den with den[y][x] = sum over u,v in 0..7 (y-u, x-v >= 0) of
+/* Aggregation of the BM3D first stage (Fig. 1, Section II): out = num/den
+ * with den[y][x] = sum over u,v in 0..7 (y-u, x-v >= 0) of
  * wsum[y-u][x-v]*K(u)*K(v), K the Kaiser window of p->kaiser_beta (only that
- * field of p is used; p must still pass validation).  final_step = 0: out is
- * planar [c][h][w] (the basic estimate).  final_step = 1: out is HWC
- * [h][w][c], opponent channels mapped back to RGB with the transpose of the
- * opponent matrix. */
-int bm3d_aggregate(const float* num, const float* wsum, int h, int w, int c, int final_step,
+ * field of p is used; p must still pass validation); num/wsum as written by
+ * bm3d_collab_filter.  final_step = 0: out is device planar float
+ * [c][h][w] (the basic estimate).  final_step = 1: out is HWC [h][w][c],
+ * opponent channels mapped back to RGB with the transpose of the opponent
+ * matrix. */
+int bm3d_aggregate(const int64_t* num, const int64_t* wsum, int h, int w, int c, int final_step,
                    const bm3d_params* p, float* out, bm3d_stream_t stream);
 
 /* Step-2 matching luminance from a planar basic estimate: the grey channel,
  * or the first opponent channel / sqrt3 (= mean of R,G,B).  lum: float [h][w]. */
 int bm3d_luminance(const float* basic, int h, int w, int c, float* lum, bm3d_stream_t stream);
 
-/* Whole two-step denoiser on one image.  img: HWC uint8; out: HWC float.
- * Uses params->workspace (>= bm3d_workspace_size bytes). */
+/* Whole two-step denoiser on one image: BM3D(y), the first-stage estimate of
+ * eqs. (2)-(3) (Section II), for y = x + n with n white Gaussian of standard
+ * deviation sigma on the [0,255] scale (eq. (1)), sigma given by the caller.
+ * img: device HWC uint8; out: device HWC float, unclipped.  Uses
+ * params->workspace (>= bm3d_workspace_size bytes, BM3D_ERR_WORKSPACE
+ * otherwise), which afterwards holds every working buffer
+ * (bm3d_workspace_buffer).  Allocates nothing, makes no synchronisation;
+ * graph-capturable. */
 int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_params* params,
                  float* out, bm3d_stream_t stream);
 
@@ -382,6 +438,14 @@ int bm3d_batch_launch(bm3d_batch* plan, bm3d_stream_t stream);
  * stage-level continuous batching in the serving loop. */
 int bm3d_batch_run_stages(bm3d_batch* plan, int i0, int i1, int first, int last,
                           bm3d_stream_t stream);
+/* Copies working buffer `buffer` (bm3d_buffer) of image i between the plan
+ * and the caller's device memory `dev` (to_plan = 0: plan -> dev; 1: dev ->
+ * plan), asynchronously on `stream`.  bytes must equal the buffer's size
+ * (bm3d_workspace_buffer of the image's shape and the plan's params),
+ * BM3D_ERR_ARG otherwise.  For tests and inspection: reading the groups and
+ * estimates a run produced, or setting the groups a later stage uses. */
+int bm3d_batch_copy_buffer(bm3d_batch* plan, int i, int buffer, void* dev, size_t bytes, int to_plan,
+                           bm3d_stream_t stream);
 int bm3d_batch_destroy(bm3d_batch* plan);
 
 /* ---- serving: stage-level continuous batching ----

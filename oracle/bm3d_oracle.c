@@ -292,7 +292,7 @@ void orc_match_f64(const double* lum, int h, int w, int S, int nmax, double tau,
  * (1 if nothing is kept).  step 2: empirical Wiener shrinkage
  * W = B^2/(B^2+sigma^2) (1 where the denominator is 0) of the noisy
  * spectrum, with B the spectrum of the basic estimate over the same patches,
- * weight 1/sum(W^2) (1 if that is 0).  Weights are per channel.  Each filtered
+ * weight 1/max(sum(W^2), 2^-10) (the step-2 weight capped at 2^10).  Weights are per channel.  Each filtered
  * patch is added into num with weight w*K(u)K(v) and w*K(u)K(v) into den,
  * K the Kaiser window.  num/den are accumulated (+=).  margin (optional,
  * step 1) receives, per reference, min over channels and coefficients of
@@ -357,7 +357,10 @@ void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
             s[e] *= W;
             sw2 += W * W;
           }
-          weight = sw2 > 0.0 ? 1.0 / sw2 : 1.0;
+          /* 1/sum W^2, capped at 2^10: a group whose pilot spectrum is all
+           * but zero filters to ~0 whatever its weight (and 1/0 stays
+           * defined) */
+          weight = 1.0 / (sw2 > 0x1p-10 ? sw2 : 0x1p-10);
         }
         orc_transform3d(s, n, g, 1);
         memcpy(est + ((size_t)ci * c + k) * nmax * 64, g, sizeof(double) * n * 64);

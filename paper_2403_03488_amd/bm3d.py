@@ -22,7 +22,15 @@ _lib = ctypes.CDLL(LIB_PATH)
 XF_FP32, XF_BF16, XF_FP16 = 0, 1, 2
 FLAG_DEBUG_SYNC = 1
 FLAG_SIGMA_PROFILE = 2
+FLAG_DEBUG_NKEPT = 4
 STAGES = ("prep", "match1", "filter1", "agg1", "match2", "filter2", "agg2")
+# working buffers of a workspace / batched plan (bm3d_buffer), with their
+# element types; num and wsum are fixed point with NUM_FRAC_BITS / WSUM_FRAC_BITS
+# fractional bits
+BUFFERS = ("planar", "lum8", "lumf", "basic", "num", "wsum", "idx1", "cnt1", "idx2", "cnt2", "nkept")
+BUFFER_DTYPES = ("float32", "uint8", "float32", "float32", "int64", "int64", "int32", "int32", "int32", "int32",
+                 "int32")
+NUM_FRAC_BITS, WSUM_FRAC_BITS = 28, 40
 
 
 class Params(ctypes.Structure):
@@ -87,6 +95,7 @@ _SIGS = {
     "bm3d_params_default": (_i, [_f, _PP]),
     "bm3d_num_refs": (_i, [_i, _i]),
     "bm3d_workspace_size": (_sz, [_i, _i, _i, _PP]),
+    "bm3d_workspace_buffer": (_i, [_i, _i, _i, _PP, _i, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
     "bm3d_prepare": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "bm3d_block_match": (_i, [_vp, _i, _i, _i, _i, _PP, _vp, _vp, _vp]),
     "bm3d_collab_filter": (_i, [_vp, _vp, _i, _i, _i, _f, _i, _vp, _vp, _PP, _vp, _vp, _vp]),
@@ -115,6 +124,7 @@ _SIGS = {
     "bm3d_vst_denoise": (_i, [_vp, _i, _i, _i, ctypes.POINTER(GatParams), _PP, _vp, _vp, _vp]),
     "bm3d_batch_create": (_i, [ctypes.POINTER(ImageDesc), _i, _PP, ctypes.POINTER(_vp)]),
     "bm3d_batch_device_bytes": (_sz, [_vp]),
+    "bm3d_batch_copy_buffer": (_i, [_vp, _i, _i, _vp, _sz, _i, _vp]),
     "bm3d_batch_set_io": (_i, [_vp, _i, _vp, _vp, _vp]),
     "bm3d_batch_run": (_i, [_vp, _vp]),
     "bm3d_batch_capture": (_i, [_vp, _vp]),
@@ -155,7 +165,10 @@ def _stream(stream):
     return stream if isinstance(stream, int) else stream.cuda_stream
 
 
-def _ptr(t, dtype=None, name="tensor"):
+def _ptr(t, dtype=None, name="tensor", numel=None, exact=False):
+    """Device pointer of a contiguous tensor of the given dtype; with numel,
+    the tensor must hold at least (exact: exactly) that many elements, so a
+    kernel never writes past a caller's buffer."""
     if t is None:
         return None
     if not t.is_cuda:
@@ -164,7 +177,18 @@ def _ptr(t, dtype=None, name="tensor"):
         raise ValueError("%s must be contiguous" % name)
     if dtype is not None and t.dtype != dtype:
         raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and (t.numel() != numel if exact else t.numel() < numel):
+        raise ValueError("%s must have %s%d elements, got %d" % (name, "" if exact else "at least ", numel,
+                                                                 t.numel()))
     return t.data_ptr()
+
+
+def _hwc(img, name="img"):
+    if img.dim() == 2:
+        return img.shape[0], img.shape[1], 1
+    if img.dim() == 3 and img.shape[2] in (1, 3):
+        return img.shape[0], img.shape[1], img.shape[2]
+    raise ValueError("%s must be [h,w] or [h,w,c] with c in (1, 3), got %s" % (name, tuple(img.shape)))
 
 
 def params_default(sigma: float, **overrides) -> Params:
@@ -183,6 +207,24 @@ def workspace_size(h: int, w: int, c: int, p: Params) -> int:
     return _lib.bm3d_workspace_size(h, w, c, ctypes.byref(p))
 
 
+def workspace_buffer(h: int, w: int, c: int, p: Params, buffer: str):
+    """(byte offset, bytes) of a working buffer inside bm3d_denoise's workspace."""
+    off, nb = _sz(), _sz()
+    _check(_lib.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), BUFFERS.index(buffer), ctypes.byref(off),
+                                      ctypes.byref(nb)), "bm3d_workspace_buffer")
+    return off.value, nb.value
+
+
+def workspace_view(workspace, h: int, w: int, c: int, p: Params, buffer: str):
+    """A typed view (1-D tensor) of one working buffer inside a device
+    workspace tensor, e.g. the step-1 groups after bm3d_denoise."""
+    torch = _torch()
+    off, nb = workspace_buffer(h, w, c, p, buffer)
+    if off + nb > workspace.numel():
+        raise ValueError("workspace too small for %s" % buffer)
+    return workspace[off:off + nb].view(getattr(torch, BUFFER_DTYPES[BUFFERS.index(buffer)]))
+
+
 def strerror(status: int) -> str:
     return _lib.bm3d_strerror(status).decode()
 
@@ -192,68 +234,81 @@ def strerror(status: int) -> str:
 def prepare(img, planar, lum, stream=None):
     """img: uint8 [h,w] or [h,w,3]; planar: float32 [c,h,w]; lum: uint8 [h,w]."""
     torch = _torch()
-    h, w = img.shape[0], img.shape[1]
-    c = 1 if img.dim() == 2 else img.shape[2]
+    h, w, c = _hwc(img)
     _check(_lib.bm3d_prepare(_ptr(img, torch.uint8, "img"), h, w, c,
-                             _ptr(planar, torch.float32, "planar"), _ptr(lum, torch.uint8, "lum"),
-                             _stream(stream)), "bm3d_prepare")
+                             _ptr(planar, torch.float32, "planar", c * h * w, True),
+                             _ptr(lum, torch.uint8, "lum", h * w, True), _stream(stream)), "bm3d_prepare")
 
 
 def block_match(src, step: int, p: Params, idx, cnt, stream=None):
     torch = _torch()
+    if src.dim() != 2:
+        raise ValueError("src must be a [h,w] luminance")
     h, w = src.shape
     is_f32 = 1 if src.dtype == torch.float32 else 0
-    _check(_lib.bm3d_block_match(_ptr(src, None, "src"), is_f32, h, w, step, ctypes.byref(p),
-                                 _ptr(idx, torch.int32, "idx"), _ptr(cnt, torch.int32, "cnt"),
-                                 _stream(stream)), "bm3d_block_match")
+    R = num_refs(h, w)
+    nmax = p.n_ht if step == 1 else p.n_wie
+    _check(_lib.bm3d_block_match(_ptr(src, torch.float32 if is_f32 else torch.uint8, "src"), is_f32, h, w, step,
+                                 ctypes.byref(p), _ptr(idx, torch.int32, "idx", R * nmax),
+                                 _ptr(cnt, torch.int32, "cnt", R), _stream(stream)), "bm3d_block_match")
 
 
 def collab_filter(noisy, basic, sigma: float, step: int, idx, cnt, p: Params, num, wsum,
                   stream=None):
+    """num/wsum: int64 fixed-point accumulators [c,h,w] (added into)."""
     torch = _torch()
     c, h, w = noisy.shape
+    R = num_refs(h, w)
+    nmax = p.n_ht if step == 1 else p.n_wie
     _check(_lib.bm3d_collab_filter(_ptr(noisy, torch.float32, "noisy"),
-                                   _ptr(basic, torch.float32, "basic"), h, w, c, float(sigma),
-                                   step, _ptr(idx, torch.int32, "idx"),
-                                   _ptr(cnt, torch.int32, "cnt"), ctypes.byref(p),
-                                   _ptr(num, torch.float32, "num"),
-                                   _ptr(wsum, torch.float32, "wsum"), _stream(stream)),
+                                   _ptr(basic, torch.float32, "basic", c * h * w, True), h, w, c, float(sigma),
+                                   step, _ptr(idx, torch.int32, "idx", R * nmax),
+                                   _ptr(cnt, torch.int32, "cnt", R), ctypes.byref(p),
+                                   _ptr(num, torch.int64, "num", c * h * w, True),
+                                   _ptr(wsum, torch.int64, "wsum", c * h * w, True), _stream(stream)),
            "bm3d_collab_filter")
 
 
 def aggregate(num, wsum, final_step: bool, p: Params, out, stream=None):
     torch = _torch()
     c, h, w = num.shape
-    _check(_lib.bm3d_aggregate(_ptr(num, torch.float32, "num"), _ptr(wsum, torch.float32, "wsum"),
+    _check(_lib.bm3d_aggregate(_ptr(num, torch.int64, "num"), _ptr(wsum, torch.int64, "wsum", c * h * w, True),
                                h, w, c, 1 if final_step else 0, ctypes.byref(p),
-                               _ptr(out, torch.float32, "out"), _stream(stream)), "bm3d_aggregate")
+                               _ptr(out, torch.float32, "out", c * h * w, True), _stream(stream)),
+           "bm3d_aggregate")
+
+
+def from_fix(t, buffer: str):
+    """Real values (float64) of a fixed-point accumulator tensor ("num" or "wsum")."""
+    return t.double() * 2.0 ** -(NUM_FRAC_BITS if buffer == "num" else WSUM_FRAC_BITS)
 
 
 def luminance(basic, lum, stream=None):
     torch = _torch()
     c, h, w = basic.shape
     _check(_lib.bm3d_luminance(_ptr(basic, torch.float32, "basic"), h, w, c,
-                               _ptr(lum, torch.float32, "lum"), _stream(stream)), "bm3d_luminance")
+                               _ptr(lum, torch.float32, "lum", h * w, True), _stream(stream)), "bm3d_luminance")
 
 
 def denoise(img, sigma: float, p: Params | None = None, out=None, workspace=None, stream=None):
     """Two-step denoiser on one device image (uint8 [h,w] or [h,w,3]).
-    Returns a float32 device tensor of the same shape on the [0,255] scale."""
+    Returns a float32 device tensor of the same shape on the [0,255] scale.
+    A workspace tensor passed in holds the working buffers afterwards
+    (workspace_view)."""
     torch = _torch()
-    h, w = img.shape[0], img.shape[1]
-    c = 1 if img.dim() == 2 else img.shape[2]
+    h, w, c = _hwc(img)
     p = (p or params_default(sigma)).copy()
     need = workspace_size(h, w, c, p)
     if need == 0:
         raise BM3DError(-1, "bm3d_workspace_size")
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=img.device)
-    p.workspace = workspace.data_ptr()
+    p.workspace = _ptr(workspace, torch.uint8, "workspace")
     p.workspace_bytes = workspace.numel()
     if out is None:
         out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
     _check(_lib.bm3d_denoise(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma),
-                             ctypes.byref(p), _ptr(out, torch.float32, "out"), _stream(stream)),
+                             ctypes.byref(p), _ptr(out, torch.float32, "out", h * w * c, True), _stream(stream)),
            "bm3d_denoise")
     return out
 
@@ -497,8 +552,7 @@ def vst_denoise(raw, g: GatParams, p: Params | None = None, out=None, stab=None,
     """x_hat of a raw Poisson-Gaussian device image (float [h,w] or
     [h,w,3]): stabilise, BM3D at the 8-bit noise level, unbiased inverse."""
     torch = _torch()
-    h, w = raw.shape[0], raw.shape[1]
-    c = 1 if raw.dim() == 2 else raw.shape[2]
+    h, w, c = _hwc(raw, "raw")
     p = (p or params_default(gat_noise_level(g.scale))).copy()
     need = workspace_size(h, w, c, p)
     if need == 0:
@@ -512,7 +566,8 @@ def vst_denoise(raw, g: GatParams, p: Params | None = None, out=None, stab=None,
     if stab is None:
         stab = torch.empty(raw.shape, dtype=torch.uint8, device=raw.device)
     _check(_lib.bm3d_vst_denoise(_ptr(raw, torch.float32, "raw"), h, w, c, ctypes.byref(g), ctypes.byref(p),
-                                 _ptr(stab, torch.uint8, "stab"), _ptr(out, torch.float32, "out"), _stream(stream)),
+                                 _ptr(stab, torch.uint8, "stab", h * w * c, True),
+                                 _ptr(out, torch.float32, "out", h * w * c, True), _stream(stream)),
            "bm3d_vst_denoise")
     return out
 
@@ -530,13 +585,18 @@ class Batch:
     """A batched plan over many images of different shapes (bm3d_batch_*)."""
 
     def __init__(self, images, outs, sigmas, p: Params):
+        torch = _torch()
         self.n = len(images)
+        self.p = p.copy()
         arr = (ImageDesc * self.n)()
+        self.shapes = []
         for i, (im, o, s) in enumerate(zip(images, outs, sigmas)):
-            c = 1 if im.dim() == 2 else im.shape[2]
-            arr[i] = ImageDesc(_ptr(im, None, "img"), _ptr(o, None, "out"), im.shape[0],
-                               im.shape[1], c, float(s))
-        self._keep = (images, outs)
+            h, w, c = _hwc(im)
+            arr[i] = ImageDesc(_ptr(im, torch.uint8, "img"), _ptr(o, torch.float32, "out", h * w * c, True), h, w,
+                               c, float(s))
+            self.shapes.append((h, w, c))
+        # the plan reads and writes these until it is closed or re-bound
+        self._keep = [[im, o] for im, o in zip(images, outs)]
         self._h = ctypes.c_void_p()
         _check(_lib.bm3d_batch_create(arr, self.n, ctypes.byref(p), ctypes.byref(self._h)),
                "bm3d_batch_create")
@@ -546,8 +606,16 @@ class Batch:
         return _lib.bm3d_batch_device_bytes(self._h)
 
     def set_io(self, i: int, img, out, stream=None):
-        _check(_lib.bm3d_batch_set_io(self._h, i, _ptr(img, None, "img"), _ptr(out, None, "out"),
-                                      _stream(stream)), "bm3d_batch_set_io")
+        torch = _torch()
+        if not 0 <= i < self.n:
+            raise ValueError("image index %d out of range" % i)
+        if _hwc(img) != self.shapes[i]:
+            raise ValueError("set_io: image %d must keep its shape %s" % (i, self.shapes[i]))
+        h, w, c = self.shapes[i]
+        _check(_lib.bm3d_batch_set_io(self._h, i, _ptr(img, torch.uint8, "img"),
+                                      _ptr(out, torch.float32, "out", h * w * c, True), _stream(stream)),
+               "bm3d_batch_set_io")
+        self._keep[i] = [img, out]
 
     def run(self, stream=None):
         _check(_lib.bm3d_batch_run(self._h, _stream(stream)), "bm3d_batch_run")
@@ -555,6 +623,28 @@ class Batch:
     def run_stages(self, i0: int, i1: int, first: int, last: int, stream=None):
         _check(_lib.bm3d_batch_run_stages(self._h, i0, i1, first, last, _stream(stream)),
                "bm3d_batch_run_stages")
+
+    def buffer_bytes(self, i: int, buffer: str) -> int:
+        h, w, c = self.shapes[i]
+        return workspace_buffer(h, w, c, self.p, buffer)[1]
+
+    def read_buffer(self, i: int, buffer: str, stream=None):
+        """A device copy (1-D, typed) of image i's working buffer."""
+        torch = _torch()
+        nb = self.buffer_bytes(i, buffer)
+        t = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        _check(_lib.bm3d_batch_copy_buffer(self._h, i, BUFFERS.index(buffer), t.data_ptr(), nb, 0,
+                                           _stream(stream)), "bm3d_batch_copy_buffer")
+        return t.view(getattr(torch, BUFFER_DTYPES[BUFFERS.index(buffer)]))
+
+    def write_buffer(self, i: int, buffer: str, src, stream=None):
+        """Sets image i's working buffer from a device tensor of its exact size."""
+        torch = _torch()
+        dt = getattr(torch, BUFFER_DTYPES[BUFFERS.index(buffer)])
+        nb = self.buffer_bytes(i, buffer)
+        _check(_lib.bm3d_batch_copy_buffer(self._h, i, BUFFERS.index(buffer),
+                                           _ptr(src, dt, buffer, nb // src.element_size(), True), nb, 1,
+                                           _stream(stream)), "bm3d_batch_copy_buffer")
 
     def capture(self, stream=None):
         _check(_lib.bm3d_batch_capture(self._h, _stream(stream)), "bm3d_batch_capture")

@@ -25,6 +25,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool is_pow2_upto32(int n) { return n >= 1 && n <= 32 && (n & (n - 1)) == 0; }
 
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr float kMaxKaiserBeta = 50.f;
 
 int auto_tile(int S) { return S >= 24 ? 4 : 6; }
 
@@ -44,6 +45,9 @@ int check_params(const bm3d_params* p) {
   if (!(p->lambda_ht >= 0.f) || !isfinite(p->lambda_ht)) return BM3D_ERR_ARG;
   if (!(p->tau_ht >= 0.f) || !(p->tau_wie >= 0.f)) return BM3D_ERR_ARG;  // NaN fails
   if (!(p->kaiser_beta >= 0.f) || !isfinite(p->kaiser_beta)) return BM3D_ERR_ARG;
+  // above this the FP32 corner weight K(0)^2 falls towards the subnormal
+  // range (it underflows near beta = 90), and the denominators with it
+  if (p->kaiser_beta > kMaxKaiserBeta) return BM3D_ERR_UNSUPPORTED;
   if (p->xform < BM3D_XF_FP32 || p->xform > BM3D_XF_FP16) return BM3D_ERR_ARG;
   if (p->tile_refs < 0 || p->tile_refs > 16) return BM3D_ERR_ARG;
   if (p->persistent_wgs < 0 || p->persistent_wgs > 64) return BM3D_ERR_ARG;
@@ -115,40 +119,47 @@ int run(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s
   return launch_single(stage, xform, d, kp, s, sync) == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
 
-// workspace carve-up of one image
+// workspace carve-up of one image: offset and size of every bm3d_buffer
+// (the kept-coefficient counts only with BM3D_FLAG_DEBUG_NKEPT)
 struct Layout {
-  size_t planar, lum8, lumf, basic, num, wsum, idx1, cnt1, idx2, cnt2, total;
+  size_t off[BM3D_NUM_BUFFERS], bytes[BM3D_NUM_BUFFERS], total;
 };
 Layout layout(int h, int w, int c, const bm3d_params* p) {
-  size_t hw = (size_t)h * w;
-  size_t R = (size_t)ref_count_1d(h) * ref_count_1d(w);
+  const size_t hw = (size_t)h * w;
+  const size_t R = (size_t)ref_count_1d(h) * ref_count_1d(w);
   Layout L;
+  L.bytes[BM3D_BUF_PLANAR] = c * hw * 4;
+  L.bytes[BM3D_BUF_LUM8] = hw;
+  L.bytes[BM3D_BUF_LUMF] = hw * 4;
+  L.bytes[BM3D_BUF_BASIC] = c * hw * 4;
+  L.bytes[BM3D_BUF_NUM] = c * hw * 8;
+  L.bytes[BM3D_BUF_WSUM] = c * hw * 8;
+  L.bytes[BM3D_BUF_IDX1] = R * p->n_ht * 4;
+  L.bytes[BM3D_BUF_CNT1] = R * 4;
+  L.bytes[BM3D_BUF_IDX2] = R * p->n_wie * 4;
+  L.bytes[BM3D_BUF_CNT2] = R * 4;
+  L.bytes[BM3D_BUF_NKEPT] = (p->flags & BM3D_FLAG_DEBUG_NKEPT) ? c * R * 4 : 0;
   size_t o = 0;
-  L.planar = o; o += align_up(c * hw * 4);
-  L.lum8 = o;   o += align_up(hw);
-  L.lumf = o;   o += align_up(hw * 4);
-  L.basic = o;  o += align_up(c * hw * 4);
-  L.num = o;    o += align_up(c * hw * 4);
-  L.wsum = o;   o += align_up(c * hw * 4);
-  L.idx1 = o;   o += align_up(R * p->n_ht * 4);
-  L.cnt1 = o;   o += align_up(R * 4);
-  L.idx2 = o;   o += align_up(R * p->n_wie * 4);
-  L.cnt2 = o;   o += align_up(R * 4);
+  for (int b = 0; b < BM3D_NUM_BUFFERS; b++) {
+    L.off[b] = o;
+    o += align_up(L.bytes[b]);
+  }
   L.total = o;
   return L;
 }
 
 void bind_workspace(ImgDesc& d, char* base, const Layout& L) {
-  d.planar = (float*)(base + L.planar);
-  d.lum8 = (uint8_t*)(base + L.lum8);
-  d.lumf = (float*)(base + L.lumf);
-  d.basic = (float*)(base + L.basic);
-  d.num = (float*)(base + L.num);
-  d.wsum = (float*)(base + L.wsum);
-  d.idx1 = (int32_t*)(base + L.idx1);
-  d.cnt1 = (int32_t*)(base + L.cnt1);
-  d.idx2 = (int32_t*)(base + L.idx2);
-  d.cnt2 = (int32_t*)(base + L.cnt2);
+  d.planar = (float*)(base + L.off[BM3D_BUF_PLANAR]);
+  d.lum8 = (uint8_t*)(base + L.off[BM3D_BUF_LUM8]);
+  d.lumf = (float*)(base + L.off[BM3D_BUF_LUMF]);
+  d.basic = (float*)(base + L.off[BM3D_BUF_BASIC]);
+  d.num = (int64_t*)(base + L.off[BM3D_BUF_NUM]);
+  d.wsum = (int64_t*)(base + L.off[BM3D_BUF_WSUM]);
+  d.idx1 = (int32_t*)(base + L.off[BM3D_BUF_IDX1]);
+  d.cnt1 = (int32_t*)(base + L.off[BM3D_BUF_CNT1]);
+  d.idx2 = (int32_t*)(base + L.off[BM3D_BUF_IDX2]);
+  d.cnt2 = (int32_t*)(base + L.off[BM3D_BUF_CNT2]);
+  d.nkept = L.bytes[BM3D_BUF_NKEPT] ? (int32_t*)(base + L.off[BM3D_BUF_NKEPT]) : nullptr;
 }
 
 }  // namespace
@@ -190,6 +201,18 @@ extern "C" size_t bm3d_workspace_size(int h, int w, int c, const bm3d_params* p)
   return layout(h, w, c, p).total;
 }
 
+extern "C" int bm3d_workspace_buffer(int h, int w, int c, const bm3d_params* p, int buffer, size_t* offset,
+                                     size_t* bytes) {
+  int e = check_image(h, w, c);
+  if (e) return e;
+  if ((e = check_params(p))) return e;
+  if (buffer < 0 || buffer >= BM3D_NUM_BUFFERS || !offset || !bytes) return BM3D_ERR_ARG;
+  const Layout L = layout(h, w, c, p);
+  *offset = L.off[buffer];
+  *bytes = L.bytes[buffer];
+  return BM3D_OK;
+}
+
 // ====================================================== stage entry points
 extern "C" int bm3d_prepare(const uint8_t* img, int h, int w, int c, float* planar, uint8_t* lum,
                             bm3d_stream_t stream) {
@@ -229,7 +252,7 @@ extern "C" int bm3d_block_match(const void* src, int src_is_f32, int h, int w, i
 
 extern "C" int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int c,
                                   float sigma, int step, const int32_t* idx, const int32_t* cnt,
-                                  const bm3d_params* p, float* num, float* wsum,
+                                  const bm3d_params* p, int64_t* num, int64_t* wsum,
                                   bm3d_stream_t stream) {
   int e = check_image(h, w, c);
   if (e) return e;
@@ -255,7 +278,7 @@ extern "C" int bm3d_collab_filter(const float* noisy, const float* basic, int h,
              want_sync(p));
 }
 
-extern "C" int bm3d_aggregate(const float* num, const float* wsum, int h, int w, int c,
+extern "C" int bm3d_aggregate(const int64_t* num, const int64_t* wsum, int h, int w, int c,
                               int final_step, const bm3d_params* p, float* out,
                               bm3d_stream_t stream) {
   int e = check_image(h, w, c);
@@ -263,8 +286,8 @@ extern "C" int bm3d_aggregate(const float* num, const float* wsum, int h, int w,
   if ((e = check_params(p))) return e;
   if (!num || !wsum || !out) return BM3D_ERR_ARG;
   ImgDesc d = base_desc(h, w, c, 0.f, nullptr);
-  d.num = (float*)num;
-  d.wsum = (float*)wsum;
+  d.num = (int64_t*)num;
+  d.wsum = (int64_t*)wsum;
   KParams kp = make_kparams(p);
   if (final_step) {
     d.out = out;
@@ -325,6 +348,7 @@ struct bm3d_batch {
   std::vector<int> hprefix[LIST_KINDS];
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  std::vector<size_t> base;  // offset of each image's workspace in ws
   int* ctr = nullptr;  // dynamic filter-tile counter pair (zero between launches)
   int cus = 256;
   hipGraphExec_t gexec = nullptr;
@@ -385,7 +409,8 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
   b->imgs.assign(imgs, imgs + n);
   b->cus = device_cus();
   std::vector<Layout> Ls(n);
-  std::vector<size_t> base(n);
+  std::vector<size_t>& base = b->base;
+  base.assign(n, 0);
   size_t tot = 0;
   for (int i = 0; i < n; i++) {
     Ls[i] = layout(imgs[i].h, imgs[i].w, imgs[i].c, p);
@@ -424,6 +449,17 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
 }
 
 extern "C" size_t bm3d_batch_device_bytes(const bm3d_batch* b) { return b ? b->ws_bytes : 0; }
+
+extern "C" int bm3d_batch_copy_buffer(bm3d_batch* b, int i, int buffer, void* dev, size_t bytes, int to_plan,
+                                      bm3d_stream_t stream) {
+  if (!b || i < 0 || i >= b->n || buffer < 0 || buffer >= BM3D_NUM_BUFFERS || !dev) return BM3D_ERR_ARG;
+  const Layout L = layout(b->imgs[i].h, b->imgs[i].w, b->imgs[i].c, &b->p);
+  if (L.bytes[buffer] == 0 || bytes != L.bytes[buffer]) return BM3D_ERR_ARG;
+  char* mine = b->ws + b->base[i] + L.off[buffer];
+  hipError_t e = to_plan ? hipMemcpyAsync(mine, dev, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream)
+                         : hipMemcpyAsync(dev, mine, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? BM3D_OK : BM3D_ERR_HIP;
+}
 
 extern "C" int bm3d_batch_set_io(bm3d_batch* b, int i, const uint8_t* img, float* out,
                                  bm3d_stream_t stream) {

@@ -46,8 +46,8 @@ struct ImgDesc {
   uint8_t* lum8;       // [h][w] step-1 matching luminance
   float* lumf;         // [h][w] step-2 matching luminance
   float* basic;        // [c][h][w] basic estimate
-  float* num;          // [c][h][w] aggregation numerator
-  float* wsum;         // [c][h][w] sum of group weights per patch position
+  int64_t* num;        // [c][h][w] aggregation numerator (fixed point, kNumFrac)
+  int64_t* wsum;       // [c][h][w] sum of group weights per patch position (kWsumFrac)
   int32_t* idx1;       // [R][n_ht]
   int32_t* cnt1;       // [R]
   int32_t* idx2;       // [R][n_wie]
@@ -92,8 +92,29 @@ template <class T> __device__ inline T ldc(const T* p) {
   for (int i = 0; i < (int)(sizeof(T) / 4); i++) dst[i] = src[i];
   return r;
 }
-__device__ inline void gadd(float* p, float v) {
-  __hip_atomic_fetch_add((BM3D_GLOBAL float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Aggregation accumulators (num, wsum) are signed 64-bit fixed point.
+// Integer additions are exact and associative, so the sums do not depend on
+// the order in which tiles add into them: results are reproducible bit for
+// bit, whatever the launch shape or the scheduling.  A float contribution is
+// scaled exactly by 2^FRAC in double precision and rounded to the nearest
+// integer.  Ranges: a pixel collects at most 64 patch positions x ~170
+// groups = ~11k contributions of |w K v| <= kMaxWeight * 500, so |num| < 6e9
+// (< 2^35, the range with 28 fractional bits); a patch corner collects at
+// most ~170 weights, so |wsum| < 2^18 (< 2^23, the range with 40).
+constexpr int kNumFrac = 28, kWsumFrac = 40;
+// Largest group weight: the step-2 weight 1/sum W^2 is capped here (a group
+// whose pilot spectrum is all but zero filters to ~0 whatever its weight);
+// step-1 weights are at most 1.
+constexpr float kMaxWeight = 1024.f;
+template <int FRAC> __device__ inline int64_t to_fix(float v) {
+  return (int64_t)__builtin_rint((double)v * (double)(1ull << FRAC));
+}
+template <int FRAC> __device__ inline float from_fix(int64_t n) {
+  return (float)((double)n * (1.0 / (double)(1ull << FRAC)));
+}
+template <int FRAC> __device__ inline void gadd_fix(int64_t* p, float v) {
+  __hip_atomic_fetch_add((BM3D_GLOBAL unsigned long long*)p, (unsigned long long)to_fix<FRAC>(v),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ----------------------------------------------------- wave primitives ---

@@ -65,8 +65,8 @@ __device__ void fill_chunk(const ImgDesc& d, int chunk) {
   for (int k = 0; k < 4; k++) {
     size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
     if (p < n) {
-      d.num[p] = 0.f;
-      d.wsum[p] = 0.f;
+      d.num[p] = 0;
+      d.wsum[p] = 0;
     }
   }
 }
@@ -87,12 +87,12 @@ struct AggLds {
 __device__ void agg_channel(const ImgDesc& d, const KParams& kp, int ch, int y0, int x0, AggLds& sh,
                             float (&e)[4]) {
   const size_t hw = (size_t)d.h * d.w;
-  const float* __restrict__ ws = d.wsum + ch * hw;
+  const int64_t* __restrict__ ws = d.wsum + ch * hw;
   const int tid = threadIdx.x, xx = tid & 63, wv = tid >> 6;
   for (int i = tid; i < (kAggRows + 7) * (kAggCols + 8); i += kThreads) {
     const int r = i / (kAggCols + 8), cc = i - r * (kAggCols + 8);
     const int y = y0 - 7 + r, x = x0 - 8 + cc;
-    sh.wt[r][cc] = (y >= 0 && y < d.h && x >= 0 && x < d.w) ? ws[(size_t)y * d.w + x] : 0.f;
+    sh.wt[r][cc] = (y >= 0 && y < d.h && x >= 0 && x < d.w) ? from_fix<kWsumFrac>(ws[(size_t)y * d.w + x]) : 0.f;
   }
   __syncthreads();
   for (int r = wv; r < kAggRows + 7; r += kThreads / 64) {
@@ -108,7 +108,7 @@ __device__ void agg_channel(const ImgDesc& d, const KParams& kp, int ch, int y0,
     float den = 0.f;
 #pragma unroll
     for (int u = 0; u < 8; u++) den = __builtin_fmaf(kp.kaiser[u], sh.hs[yl + 7 - u][xx], den);
-    e[k] = (y < d.h && x < d.w) ? d.num[ch * hw + (size_t)y * d.w + x] / den : 0.f;
+    e[k] = (y < d.h && x < d.w) ? from_fix<kNumFrac>(d.num[ch * hw + (size_t)y * d.w + x]) / den : 0.f;
   }
   __syncthreads();  // the LDS is reused by the next channel / item
 }
@@ -678,7 +678,11 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
         pix = 16 * (f >> 2) + lc;
         coef = 16 * (f & 3) + 4 * lq + v;
       }
-      v4[v] = Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
+      // the 2-D mean's basis value is exactly 1/8 (fl(1/sqrt8)^2 is not): the
+      // mean coefficient of integer pixels is then exact, so it sits on the
+      // same side of a threshold that is a multiple of 1/32 as in exact
+      // arithmetic (lambda sigma = 40.5, 67.5, 135 at sigma 15, 25, 50)
+      v4[v] = coef == 0 ? 0.125f : Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
       // the inverse table carries the Kaiser weight of its output pixel
       if (tab == 1) v4[v] *= kaiser[pix >> 3] * kaiser[pix & 7];
     }
@@ -710,7 +714,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
   const int RP = C::pitch(RW);             // its row pitch
   float* wst = wnum + C::rnum(S, T) * C::pitch(C::rnum(S, T));  // staging [16][kSP]
-  float* __restrict__ gwsum = d.wsum + ch * hw;
+  int64_t* __restrict__ gwsum = d.wsum + ch * hw;
 
   for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
   wave_lds_sync();
@@ -932,7 +936,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         }
       }
       sw2 = wave_sum_uniform(sw2);
-      wgt = sw2 > 0.f ? 1.f / sw2 : 1.f;
+      wgt = 1.f / fmaxf(sw2, 1.f / kMaxWeight);
     }
     if (l == 0) D2[0][0][0] -= off;
 
@@ -982,7 +986,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int v = 0; v < 4; v++) add[v] = __builtin_fmaf(kc, Kv[v], acc[v]);
         *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
       }
-      if (q == 0 && mv[gt]) gadd(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
+      if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
       wave_lds_sync();
       // four members per step (an absent member stages zeros at the region
       // corner); the writes go in member order, so where members coincide
@@ -1021,7 +1025,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
 
   // ---- flush: the region into num, four rows per iteration (all their LDS
   // reads first); pixels no member touched hold exact zeros and are skipped
-  float* gnum = d.num + ch * hw;
+  int64_t* gnum = d.num + ch * hw;
   for (int x0 = 0; x0 < RW; x0 += 64) {
     const int x = x0 + l;
     const int xc = min(x, RW - 1);  // in-range address for lanes past the region
@@ -1031,7 +1035,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       for (int k = 0; k < 4; k++) nv[k] = wnum[min(y0 + k, RH - 1) * RP + xc];
 #pragma unroll
       for (int k = 0; k < 4; k++)
-        if (y0 + k < RH && x < RW && nv[k] != 0.f) gadd(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
+        if (y0 + k < RH && x < RW && nv[k] != 0.f) gadd_fix<kNumFrac>(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
     }
   }
   wave_lds_sync();

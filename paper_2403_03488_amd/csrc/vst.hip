@@ -147,6 +147,11 @@ extern "C" float bm3d_gat_noise_level(float scale) { return std::sqrt(scale * sc
 extern "C" int bm3d_vst_denoise(const float* raw, int h, int w, int c, const bm3d_gat_params* g,
                                 const bm3d_params* p, uint8_t* stab, float* out, bm3d_stream_t stream) {
   if (!raw || !stab || !out || !p || h < 1 || w < 1 || (c != 1 && c != 3) || !valid(g)) return BM3D_ERR_ARG;
+  // everything bm3d_denoise checks is checked here first, so that a failing
+  // call enqueues nothing (no half-written stab)
+  const size_t need = bm3d_workspace_size(h, w, c, p);  // 0: image too small or invalid params
+  if (need == 0) return BM3D_ERR_ARG;
+  if (!p->workspace || p->workspace_bytes < need) return BM3D_ERR_WORKSPACE;
   const long long n = (long long)h * w * c;
   int e = bm3d_gat_forward(raw, n, g, stab, stream);
   if (e == BM3D_OK) e = bm3d_denoise(stab, h, w, c, bm3d_gat_noise_level(g->scale), p, out, stream);

@@ -38,6 +38,7 @@ class Request:
     admitted: float = math.nan
     done: float = math.nan
     out: object = None      # device float32 result (kept if keep_outputs)
+    buffers: object = None  # (device input, output, workspace) (kept if keep_buffers)
 
     @property
     def h(self):
@@ -63,13 +64,14 @@ def footprint(h: int, w: int, c: int, p: bm3d.Params) -> int:
 
 class ServingLoop:
     def __init__(self, p: bm3d.Params, max_slots: int = 32, hbm_budget: int = 16 << 30,
-                 keep_outputs: bool = False):
+                 keep_outputs: bool = False, keep_buffers: bool = False):
         import torch
         self.torch = torch
         self.p = p
         self.max_slots = max_slots
         self.budget = hbm_budget
         self.keep_outputs = keep_outputs
+        self.keep_buffers = keep_buffers  # inspection: the request's workspace holds its groups
         self.server = bm3d.Server(max_slots, p)
         self.stream = torch.cuda.Stream()
         self.used = 0
@@ -139,8 +141,10 @@ class ServingLoop:
                     for r, ev, bufs in finishing:
                         if ev.query():
                             r.done = time.perf_counter() - t0
-                            if self.keep_outputs:
+                            if self.keep_outputs or self.keep_buffers:
                                 r.out = bufs[1]
+                            if self.keep_buffers:
+                                r.buffers = bufs[:3]
                             self.used -= bufs[3]
                         else:
                             keep.append([r, ev, bufs])

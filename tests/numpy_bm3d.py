@@ -102,8 +102,8 @@ def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0):
                 den_w = B * B + sigma * sigma
                 W = np.where(den_w > 0, B * B / np.where(den_w > 0, den_w, 1.0), 1.0)
                 S = W * S
-                s2 = float((W * W).sum())
-                wt = 1.0 / s2 if s2 > 0 else 1.0
+                # the Wiener weight 1/sum W^2, capped at 2^10
+                wt = 1.0 / max(float((W * W).sum()), 2.0 ** -10)
             E = it3d(S)
             for m, (y, x) in enumerate(zip(ys, xs)):
                 num[k, y:y + 8, x:x + 8] += wt * K * E[m]

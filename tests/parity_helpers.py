@@ -61,6 +61,44 @@ def kaiser_den(wsum, beta):
     return den
 
 
+# fixed-point accumulators: value = integer * 2^-frac (num: 28, wsum: 40 bits)
+FRAC = {"num": 28, "wsum": 40}
+
+
+def from_fix(a, buffer):
+    """Real values (float64) of int64 fixed-point accumulators."""
+    return np.asarray(a).astype(np.float64) * 2.0 ** -FRAC[buffer]
+
+
+def to_fix(a, buffer):
+    """Nearest fixed-point integers of real values."""
+    return np.rint(np.asarray(a, np.float64) * 2.0 ** FRAC[buffer]).astype(np.int64)
+
+
+def oracle_params(sigma, S=32):
+    """The oracle's parameters for a noise level, with the values the HIP
+    path receives: lambda = 2.7 rounded to FP32, as in bm3d_params.  Some
+    spectral coefficients (the 2-D mean of a group, along any Walsh row) are
+    exact multiples of 1/32, and so is lambda*sigma at these noise levels:
+    an exact tie is not kept (strict >).  With lambda as the FP32 value the
+    FP64 oracle's threshold sits just above the tie, as the exact rule
+    says; with lambda = 2.7 in FP64 its rounding would keep some of them."""
+    import oracle
+    p = oracle.Params.for_sigma(sigma, S)
+    p.lambda_ht = float(np.float32(p.lambda_ht))
+    return p
+
+
+def anchored_masks(idx1, cnt1, flips, idx2, cnt2, h, w):
+    """Pixels an FP32 run may legitimately change: those aggregated from the
+    step-1 groups whose threshold decision differs (a near-tie), and then
+    every pixel of a step-2 group that reads one of them (through the basic
+    estimate).  Returns (step-1 mask, final mask)."""
+    m1 = patch_cover(idx1, cnt1, flips, h, w)
+    t2 = groups_touching(idx2, cnt2, m1, h, w)
+    return m1, patch_cover(idx2, cnt2, t2, h, w)
+
+
 def all_patches(plane):
     h, w = plane.shape
     return sliding_window_view(np.asarray(plane, np.float64), (8, 8)).reshape(h - 7, w - 7, 64)

@@ -191,6 +191,17 @@ def test_vst_validation_on_host(B):
     p = B.params_default(25.0)
     assert L.bm3d_vst_denoise(fake, 0, 64, 1, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -1
     assert L.bm3d_vst_denoise(fake, 64, 64, 2, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -1
+    # everything the BM3D stage checks is checked before the forward map is
+    # enqueued: a too-small image or workspace fails without a launch (a
+    # launch here, without a GPU, would report a HIP error instead)
+    assert L.bm3d_vst_denoise(fake, 4, 64, 1, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -1
+    assert L.bm3d_vst_denoise(fake, 64, 64, 1, ctypes.byref(g), ctypes.byref(p), fake, fake, None) == -3
+    small = p.copy()
+    small.workspace, small.workspace_bytes = 0x2000, 100
+    assert L.bm3d_vst_denoise(fake, 64, 64, 1, ctypes.byref(g), ctypes.byref(small), fake, fake, None) == -3
+    bad = p.copy()
+    bad.n_ht = 5
+    assert L.bm3d_vst_denoise(fake, 64, 64, 1, ctypes.byref(g), ctypes.byref(bad), fake, fake, None) == -1
     assert abs(L.bm3d_gat_noise_level(6.0) - math.sqrt(36 + 1 / 12)) < 1e-5
 
 
@@ -221,6 +232,12 @@ def test_host_validation_rejects_before_enqueue(B):
     big = p.copy()
     big.tile_refs = 16  # legal range, but its LDS footprint does not fit
     assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(big), fake, None) == -2
+    # a Kaiser window so sharp that the FP32 corner weights approach underflow
+    sharp = p.copy()
+    sharp.kaiser_beta = 60.0
+    assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(sharp), fake, None) == -2
+    sharp.kaiser_beta = 50.0  # the largest accepted value passes validation (then the workspace check fails)
+    assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(sharp), fake, None) == -3
     # stage entry points
     assert L.bm3d_block_match(fake, 1, 64, 64, 1, ref(p), fake, fake, None) == -1  # step 1 needs uint8
     assert L.bm3d_block_match(fake, 0, 64, 64, 3, ref(p), fake, fake, None) == -1
@@ -240,12 +257,72 @@ def test_host_validation_rejects_before_enqueue(B):
     assert L.bm3d_batch_run(None, None) == -1
     assert L.bm3d_batch_launch(None, None) == -1
     assert L.bm3d_batch_run_stages(None, 0, 1, 0, 6, None) == -1
+    assert L.bm3d_batch_copy_buffer(None, 0, 6, fake, 64, 0, None) == -1
+
+
+def test_workspace_buffers(B):
+    """The workspace carve-up: every buffer 256-byte aligned, in order, no
+    overlap, sized from the image and params; the kept-count region only
+    with the debug flag."""
+    p = B.params_default(25.0)
+    h, w, c = 37, 53, 3
+    R = B.num_refs(h, w)
+    want = {"planar": 4 * c * h * w, "lum8": h * w, "lumf": 4 * h * w, "basic": 4 * c * h * w,
+            "num": 8 * c * h * w, "wsum": 8 * c * h * w, "idx1": 4 * R * p.n_ht, "cnt1": 4 * R,
+            "idx2": 4 * R * p.n_wie, "cnt2": 4 * R, "nkept": 0}
+    end = 0
+    for name in B.BUFFERS:
+        off, nb = B.workspace_buffer(h, w, c, p, name)
+        assert off % 256 == 0 and off >= end and nb == want[name], name
+        end = off + nb
+    assert end <= B.workspace_size(h, w, c, p)
+    q = B.params_default(25.0, flags=B.FLAG_DEBUG_NKEPT)
+    off, nb = B.workspace_buffer(h, w, c, q, "nkept")
+    assert nb == 4 * c * R and off + nb <= B.workspace_size(h, w, c, q)
+    assert B.workspace_size(h, w, c, q) > B.workspace_size(h, w, c, p)
+    with pytest.raises(B.BM3DError):
+        B.workspace_buffer(4, w, c, p, "idx1")
+    L = B._lib
+    o, n = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), 11, ctypes.byref(o), ctypes.byref(n)) == -1
+    assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), -1, ctypes.byref(o), ctypes.byref(n)) == -1
+    assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), 0, None, ctypes.byref(n)) == -1
 
 
 def test_binding_refuses_host_tensors(B):
     torch = pytest.importorskip("torch")
     with pytest.raises(ValueError):
         B._ptr(torch.zeros(4), None, "x")
+
+
+def test_binding_checks_sizes_and_dtypes(B, monkeypatch):
+    """A wrong dtype or a buffer too small for what the kernel writes is
+    refused before the C call (host tensors posing as device tensors: the
+    checks run before any pointer is used)."""
+    torch = pytest.importorskip("torch")
+
+    class Dev:  # a stand-in with the attributes _ptr reads
+        def __init__(self, n, dtype):
+            self.t = torch.zeros(n, dtype=dtype)
+            self.is_cuda, self.dtype = True, dtype
+
+        def is_contiguous(self):
+            return True
+
+        def numel(self):
+            return self.t.numel()
+
+        def data_ptr(self):
+            return 0x1000
+
+    assert B._ptr(Dev(16, torch.float32), torch.float32, "out", 16, True) == 0x1000
+    with pytest.raises(ValueError):
+        B._ptr(Dev(15, torch.float32), torch.float32, "out", 16, True)
+    with pytest.raises(ValueError):
+        B._ptr(Dev(17, torch.float32), torch.float32, "out", 16, True)
+    assert B._ptr(Dev(17, torch.int32), torch.int32, "idx", 16) == 0x1000
+    with pytest.raises(ValueError):
+        B._ptr(Dev(16, torch.float16), torch.float32, "out", 16)
 
 
 def test_server_validation_on_host(B):
@@ -264,6 +341,7 @@ def test_footprint_model(B):
     from paper_2403_03488_amd import serve
     p = B.params_default(25.0)
     f = serve.footprint(4096, 4096, 3, p)
-    # planar, basic, num, den (4 x 12 B/px), luminances (5 B/px), in+out (15 B/px),
-    # groups (16 + 32 indices per reference, ~1 reference per 9 px: ~21 B/px)
-    assert 80 * 4096 * 4096 < f < 100 * 4096 * 4096
+    # planar, basic (2 x 12 B/px), fixed-point num, wsum (2 x 24 B/px), luminances
+    # (5 B/px), in+out (15 B/px), groups (16 + 32 indices per reference, ~1
+    # reference per 9 px: ~21 B/px)
+    assert 105 * 4096 * 4096 < f < 120 * 4096 * 4096

@@ -268,6 +268,28 @@ def test_wiener_with_noisy_pilot_closed_form():
     np.testing.assert_allclose(den, d_ref, atol=1e-12)
 
 
+def test_wiener_weight_closed_form_and_cap():
+    # one 8x8 image: a single group of one patch, so den = w K(u) K(v) exposes
+    # the group weight.  A normal pilot gives w = 1/sum W^2 with W the Wiener
+    # gains of its own spectrum; a pilot that is all but zero (gains ~1e-12)
+    # gives the capped weight 2^10; an exactly zero pilot too (1/0 capped).
+    rng = np.random.default_rng(5)
+    noisy = rng.uniform(0, 255, (1, 8, 8))
+    idx = np.zeros((1, 32), np.int32)
+    idx[0, 1:] = -1
+    cnt = np.ones(1, np.int32)
+    p = tiny_params()
+    K = np.outer(np.kaiser(8, 2.0), np.kaiser(8, 2.0))
+    for pilot, expect in ((noisy, None), (np.full_like(noisy, 1e-4), 1024.0), (np.zeros_like(noisy), 1024.0)):
+        num, den = oracle.collab_filter(noisy, pilot, 20.0, 2, idx, cnt, p)
+        if expect is None:
+            B = oracle.transform3d(pilot[0][None])
+            W = B * B / (B * B + 400.0)
+            expect = 1.0 / (W * W).sum()
+            assert expect < 1.0  # far from the cap
+        np.testing.assert_allclose(den[0] / K, expect, rtol=1e-12)
+
+
 def test_replicated_grey_colour_equals_grey_at_sigma_over_sqrt3():
     s = synth.gray_512(h=48, w=56)
     rgb = np.repeat(s.noisy[:, :, None], 3, axis=2)
