@@ -41,23 +41,38 @@ def log(*a):
 
 
 def work_models(h, w, S, cnt1, cnt2, c=1):
-    """Algorithmic work per stage for one image (see the design notes):
-    matching = int8 cross terms / FP32 SSD of every window candidate; filters =
-    the dense 3-D transform products at the actual group sizes."""
+    """Algorithmic work per stage for one image, in the separable form of the
+    method (the unit each kernel's roofline fraction is computed from):
+    matching = one multiply-add per pixel pair of every window candidate
+    (int8 cross terms in step 1, FP32 direct differences in step 2), i.e.
+    S^2 * 64 per reference; filters = the 3-D transforms with the 2-D DCT as
+    8-point row and column passes, at the actual group sizes n:
+    2048 n + 128 n^2 multiply-adds per group and channel in step 1 (forward
+    and inverse), 3 (1024 n + 64 n^2) in step 2 (noisy and basic forward,
+    inverse).  Everything is returned in operations (2 per multiply-add)."""
     def wlen(L):
         return min(S, L - 7)
     cands = len(cnt1) * wlen(h) * wlen(w)
     n1 = cnt1.astype(np.float64)
     n2 = cnt2.astype(np.float64)
-    # one dense transform of an n-patch group: 2*64*64*n (2-D DCT) + 2*64*n*n (WHT)
-    xf1 = 2.0 * 64 * n1 * (64 + n1)
-    xf2 = 2.0 * 64 * n2 * (64 + n2)
     return {
-        "match1": cands * 64 * 2.0,          # int8 ops (multiply + add)
-        "filter1": c * float(np.sum(2 * xf1)),  # forward + inverse
-        "match2": cands * 64 * 3.0,          # FP32 sub + fma per pixel pair
-        "filter2": c * float(np.sum(3 * xf2)),  # noisy + basic forward, inverse
+        "match1": 2.0 * cands * 64,
+        "filter1": 2.0 * c * float(np.sum(2048 * n1 + 128 * n1 * n1)),
+        "match2": 2.0 * cands * 64,
+        "filter2": 2.0 * c * float(np.sum(3 * (1024 * n2 + 64 * n2 * n2))),
     }
+
+
+def mfma_issued(cnt1, cnt2, c=1):
+    """Dense matrix-core operations the filters issue: each 2-D DCT is one
+    64 x 64 product per patch, each Walsh-Hadamard product runs on 16 x 16
+    tiles (groups of up to 16 members in one tile, 32 in two).  Not the
+    algorithmic work: the separable count above is."""
+    def per_group(n, srcs):
+        nt = np.where(n > 16, 32.0, 16.0)  # members padded to whole tiles
+        return srcs * (2 * 64 * 64 * nt + 2 * 64 * nt * nt) + (2 * 64 * 64 * nt + 2 * 64 * nt * nt)
+    return {"filter1": c * float(np.sum(per_group(cnt1.astype(np.float64), 1))),
+            "filter2": c * float(np.sum(per_group(cnt2.astype(np.float64), 2)))}
 
 
 # The sources each kernel family is compiled from: a counter record counts
@@ -146,6 +161,45 @@ def stage_times(torch, bm3d, plan, B, stream):
         e1.synchronize()
         stage_ms[name] = e0.elapsed_time(e1) / reps
     return stage_ms
+
+
+def cpu_baseline(args, samples, sigma, S, H, W):
+    """The FP64 C oracle on the host cores, on whole 512x512 images: first on
+    one thread, then on every core the host reports (OpenMP over reference
+    rows); about args.cpu_seconds of work in all."""
+    import oracle
+    op = oracle.Params.for_sigma(sigma, S)
+    host = os.cpu_count() or 1
+    res = {}
+    for threads in (1, host):
+        oracle.set_threads(threads)
+        n, t0 = 0, time.perf_counter()
+        while True:
+            oracle.denoise(samples[n % len(samples)].noisy, sigma, op)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds / 2 or n >= 4 * len(samples):
+                break
+        res[threads] = (n * H * W / 1e6 / el, n, el)
+        log("cpu baseline: %.4f MP/s on %d thread(s) (%d images, %.1f s)" % (res[threads][0], threads, n, el))
+    v, n, el = res[host]
+    v1, n1, el1 = res[1]
+    return {"value": v, "unit": "MP/s", "cores": host, "kind": "oracle",
+            "sample": "%d x 512x512 grey sigma=25 images, FP64 C oracle on all %d host cores (OpenMP), %.1f s"
+                      % (n, host, el),
+            "host_cores": host, "cpu_model": cpu_model(),
+            "single_thread": {"value": v1, "unit": "MP/s", "cores": 1,
+                              "sample": "%d x 512x512 grey image(s), one thread, %.1f s" % (n1, el1)}}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def tuned_params(args, bm3d, sigma, flags=0):
@@ -602,12 +656,14 @@ def ocnn_macs(K, C, H, W, F=64):
     return 9 * H * W * (2 * C * F + (K - 2) * F * F + F * C)
 
 
-def run_batch64(args):
+def measure_batch64(args, steps=None, warmup=None):
     """The mixed batch: 64 images of areas 128^2..1024^2 (aspect 1:1-2:1),
-    half grey / half colour, sigma ~ U[10,50], one captured graph per step."""
+    half grey / half colour, sigma ~ U[10,50], one captured graph per step.
+    Returns the measurement as a dict."""
     import torch
     from paper_2403_03488_amd import bm3d, synth
-    assert torch.cuda.is_available(), "no GPU"
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
     shapes = synth.batch_shapes(64)
     log("generating the 64-image mixed batch")
     samples = [synth.batch_image(i, sh) for i, sh in enumerate(shapes)]
@@ -619,14 +675,14 @@ def run_batch64(args):
     torch.cuda.set_stream(stream)
     torch.cuda.synchronize()
     plan.capture(stream)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         plan.launch(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         plan.launch(stream)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     mp = sum(s.h * s.w for s in samples) / 1e6
     cmp = sum(s.h * s.w * s.c for s in samples) / 1e6
     log("mixed batch %s: %.3f ms/step, %.1f MP/s" % (args.xform, dt * 1e3, mp / dt))
@@ -634,32 +690,41 @@ def run_batch64(args):
     plan.launch(stream)
     torch.cuda.synchronize()
     ps = [synth.psnr(s.clean, o.cpu().numpy()) for s, o in zip(samples, outs)]
+    plan.close()
+    return {"MPps": mp / dt, "ms_per_step": dt * 1e3, "steps": steps, "megapixels": mp,
+            "channel_megapixels": cmp, "channel_MPps": cmp / dt, "stages_ms": stage_ms,
+            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs,
+            "psnr_db": {"mean": float(np.mean(ps)), "min": float(np.min(ps))},
+            "workload": "64 images, areas 128^2-1024^2, aspect 1:1-2:1, half grey / half colour, "
+                        "sigma U[10,50], one graph-captured batched pass per step"}
+
+
+def run_batch64(args):
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    m = measure_batch64(args)
     res = {
-        "metric": "denoised MP/s (64-image mixed batch, both BM3D steps)", "value": mp / dt,
+        "metric": "denoised MP/s (64-image mixed batch, both BM3D steps)", "value": m["MPps"],
         "unit": "MP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.xform + "+int8", "data": "synthetic",
-        "config": {"workload": "64 images, areas 128^2-1024^2, aspect 1:1-2:1, half grey / half colour, "
-                               "sigma U[10,50], one graph-captured batched pass per step",
-                   "megapixels": mp, "channel_megapixels": cmp, "xform": args.xform,
-                   "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs},
-        "channel_MPps": cmp / dt, "stages_ms": stage_ms,
-        "psnr_db": {"mean": float(np.mean(ps)), "min": float(np.min(ps))},
+        "config": {"workload": m["workload"], "megapixels": m["megapixels"],
+                   "channel_megapixels": m["channel_megapixels"], "xform": args.xform,
+                   "tile_refs": m["tile_refs"], "persistent_wgs": m["persistent_wgs"]},
+        "channel_MPps": m["channel_MPps"], "stages_ms": m["stages_ms"], "psnr_db": m["psnr_db"],
     }
     print(json.dumps(res), flush=True)
-    plan.close()
 
 
-def run_serving(args):
-    """Serving: Poisson arrivals at 0.7x the measured batched capacity, sides
+def measure_serving(args, n=None):
+    """Serving: Poisson arrivals at args.load x the measured capacity, sides
     log-uniform 256-4096, 70 % grey, sigma U[5,60], 30 % moire.  The request
     loop (stage-level continuous batching, BF16 transforms + int8 matching)
     against the plain FP32 single-image path serving the same trace one
-    request at a time."""
+    request at a time.  Returns the measurement as a dict."""
     import torch
     from paper_2403_03488_amd import bm3d, serve, synth
-    assert torch.cuda.is_available(), "no GPU"
-    n = args.requests
+    n = n or args.requests
     log("building %d serving requests (canvases, noise, pinned inputs)" % n)
     canv = synth.serving_canvases(4096)
     noise = synth.serving_noise(4096)
@@ -697,20 +762,33 @@ def run_serving(args):
     base = serve.summarize(serve.serve_one_at_a_time(requests(1.0 / rate), p32))
     log("FP32 single-image path: %.1f MP/s, p50 %.1f ms, p99 %.1f ms" % (base["MPps"], base["p50_ms"],
                                                                         base["p99_ms"]))
+    return {"MPps": st["MPps"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "makespan_s": st["makespan_s"], "capacity_MPps": cap["MPps"], "requests": n, "mean_MP": mean_mp,
+            "load": args.load, "rate_req_s": rate, "slots": args.slots, "ticks": loop.ticks,
+            "mean_requests_per_tick": float(np.mean(loop.tick_sizes)), "peak_hbm_bytes": loop.peak_used,
+            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs,
+            "fp32_single_image_path": {"MPps": base["MPps"], "p50_ms": base["p50_ms"],
+                                       "p99_ms": base["p99_ms"], "makespan_s": base["makespan_s"]},
+            "workload": "serving: %d requests, sides log-uniform 256-4096, 70%% grey / 30%% colour, "
+                        "sigma U[5,60], 30%% moire, Poisson arrivals at %.1fx the measured capacity"
+                        % (n, args.load)}
+
+
+def run_serving(args):
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    m = measure_serving(args)
     res = {
         "metric": "served MP/s with p50/p99 latency (Poisson arrivals at %.1fx capacity)" % args.load,
-        "value": st["MPps"], "unit": "MP/s", "n_gpus": 1, "higher_is_better": True,
+        "value": m["MPps"], "unit": "MP/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": args.xform + "+int8", "data": "synthetic",
-        "config": {"workload": "serving: %d requests, sides log-uniform 256-4096, 70%% grey / 30%% colour, "
-                               "sigma U[5,60], 30%% moire, Poisson arrivals" % n,
-                   "requests": n, "mean_MP": mean_mp, "rate_req_s": rate, "slots": args.slots,
-                   "xform": args.xform, "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs},
-        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
-        "makespan_s": st["makespan_s"], "capacity_MPps": cap["MPps"],
-        "ticks": loop.ticks, "mean_requests_per_tick": float(np.mean(loop.tick_sizes)),
-        "peak_hbm_bytes": loop.peak_used,
-        "fp32_single_image_path": {"MPps": base["MPps"], "p50_ms": base["p50_ms"],
-                                   "p99_ms": base["p99_ms"], "makespan_s": base["makespan_s"]},
+        "config": {"workload": m["workload"], "requests": m["requests"], "mean_MP": m["mean_MP"],
+                   "rate_req_s": m["rate_req_s"], "slots": m["slots"], "xform": args.xform,
+                   "tile_refs": m["tile_refs"], "persistent_wgs": m["persistent_wgs"]},
+        "p50_ms": m["p50_ms"], "p99_ms": m["p99_ms"], "mean_ms": m["mean_ms"],
+        "makespan_s": m["makespan_s"], "capacity_MPps": m["capacity_MPps"],
+        "ticks": m["ticks"], "mean_requests_per_tick": m["mean_requests_per_tick"],
+        "peak_hbm_bytes": m["peak_hbm_bytes"], "fp32_single_image_path": m["fp32_single_image_path"],
     }
     print(json.dumps(res), flush=True)
 
@@ -736,6 +814,10 @@ def main():
                          "mixed batch; serving: the request loop against the FP32 single-image path; "
                          "nlm: the NL-means first stage on the 16 x 512^2 batch")
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests")
+    ap.add_argument("--default-requests", type=int, default=500,
+                    help="requests of the serving trace measured in the default run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default run: skip the mixed-batch and serving measurements")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / capacity")
     ap.add_argument("--slots", type=int, default=32, help="serving: requests in flight")
     ap.add_argument("--capacity-requests", type=int, default=300,
@@ -798,6 +880,7 @@ def main():
     # group sizes of every image (stage entry points, outside the timed region)
     R = bm3d.num_refs(H, W)
     work = {"match1": 0.0, "filter1": 0.0, "match2": 0.0, "filter2": 0.0}
+    issued = {"filter1": 0.0, "filter2": 0.0}
     planar = torch.empty((1, H, W), dtype=torch.float32, device="cuda")
     lum = torch.empty((H, W), dtype=torch.uint8, device="cuda")
     lumf = torch.empty((H, W), dtype=torch.float32, device="cuda")
@@ -817,9 +900,12 @@ def main():
         bm3d.aggregate(num, wsum, False, p, basic)
         bm3d.luminance(basic, lumf)
         bm3d.block_match(lumf, 2, p, i2, c2)
-        wm = work_models(H, W, S, c1.cpu().numpy(), c2.cpu().numpy())
+        c1h, c2h = c1.cpu().numpy(), c2.cpu().numpy()
+        wm = work_models(H, W, S, c1h, c2h)
         for k in work:
             work[k] += wm[k]
+        for k, v in mfma_issued(c1h, c2h).items():
+            issued[k] += v
     kinds = {"match1": ("mfma", "int8", PEAK["int8"], "TOP/s"),
              "match2": ("alu", "fp32_valu", PEAK["fp32_valu"], "TFLOP/s"),
              "filter1": ("mfma", args.xform, PEAK[args.xform if args.xform != "fp32" else "fp32_mfma"], "TFLOP/s"),
@@ -830,9 +916,29 @@ def main():
     roof = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": unit, "frac": achieved / peak,
             "traffic": measured_traffic(dom, B, p.tile_refs) if args.xform == "bf16" else None,
-            "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom]}
+            "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom],
+            "work_model": "separable 3-D transforms at the actual group sizes (2 ops per multiply-add)"}
+    if dom in issued:
+        roof["mfma_issued"] = {"ops_per_launch": issued[dom],
+                               "TOPps": issued[dom] / (stage_ms[dom] * 1e-3) / 1e12,
+                               "note": "dense 64x64 DCT products and 16/32-member WHT tiles as executed"}
     per_stage = {k: {"ms": stage_ms[k], "frac": (work[k] / (stage_ms[k] * 1e-3)) / kinds[k][2]}
                  for k in work}
+    # pass-level bound: the time each resource needs for the whole pass at its
+    # peak (HBM: the compulsory bytes, 13 B per grey pixel); the largest one
+    # over the measured pass time
+    need_s = {"fp32_valu (step-2 distances)": work["match2"] / PEAK["fp32_valu"],
+              "%s matrix cores (transforms)" % args.xform:
+                  (work["filter1"] + work["filter2"]) / kinds["filter1"][2],
+              "int8 matrix cores (step-1 distances)": work["match1"] / PEAK["int8"],
+              "hbm (compulsory bytes)": 13.0 * B * H * W / (PEAK["hbm_GBps"] * 1e9)}
+    binding = max(need_s, key=need_s.get)
+    pass_bound = {"binding": binding, "us_at_peak": need_s[binding] * 1e6,
+                  "us_per_MP_at_peak": need_s[binding] * 1e6 / mp, "frac": need_s[binding] / dt,
+                  "all_us_at_peak": {k: v * 1e6 for k, v in need_s.items()}}
+    log("roofline %s: %.1f %s of %.0f (%.4f); pass bound %s: %.1f us at peak, %.4f of the pass"
+        % (dom, achieved / 1e12, unit, peak / 1e12, achieved / peak, binding, need_s[binding] * 1e6,
+           need_s[binding] / dt))
 
     if args.calibrate_copy:
         calibration_copy(torch)
@@ -840,22 +946,15 @@ def main():
     if not args.quick:
         lat_ms, fp32_single, psnr32, psnrlo = single_image_checks(torch, bm3d, synth, p, imgs, outs,
                                                                   samples, sigma, H, W, B)
+    plan.close()
+    # the mixed 64-image batch and the serving trace, measured in the same run
+    mixed = serving = None
+    if not args.quick and not args.no_extra:
+        mixed = measure_batch64(args, steps=10, warmup=2)
+        serving = measure_serving(args, n=args.default_requests)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
-        oracle.set_threads(threads)
-        op = oracle.Params.for_sigma(sigma, S)
-        n, t0 = 0, time.perf_counter()
-        while True:
-            oracle.denoise(samples[n % B].noisy, sigma, op)
-            n += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds or n >= 4 * B:
-                break
-        cpu = {"value": n * H * W / 1e6 / el, "unit": "MP/s", "cores": threads, "kind": "oracle",
-               "sample": "%d x 512x512 grey sigma=25 images, FP64 C oracle, %.1f s" % (n, el)}
-        log("cpu baseline: %.4f MP/s on %d threads" % (cpu["value"], threads))
+        cpu = cpu_baseline(args, samples, sigma, S, H, W)
 
     res = {
         "metric": "denoised MP/s (both BM3D steps, sigma=25)", "value": value, "unit": "MP/s",
@@ -866,15 +965,15 @@ def main():
                                "batch of %d images per step, graph-captured batched pass" % B,
                    "batch": B, "xform": args.xform, "tile_refs": p.tile_refs,
                    "persistent_wgs": p.persistent_wgs},
-        "roofline": roof, "stages": per_stage,
+        "roofline": roof, "stages": per_stage, "pass_bound": pass_bound,
         "latency_ms_single_image": {"p50": float(np.percentile(lat_ms, 50)),
                                     "p99": float(np.percentile(lat_ms, 99))},
         "fp32_single_image_MPps": fp32_single,
         "psnr_db": {"fp32": psnr32, args.xform: psnrlo, "delta": psnrlo - psnr32},
+        "mixed_batch": mixed, "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":
