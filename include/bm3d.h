@@ -204,6 +204,21 @@ int bm3d_luminance(const float* basic, int h, int w, int c, float* lum, bm3d_str
 int bm3d_denoise(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_params* params,
                  float* out, bm3d_stream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bm3d_denoise with its
+ * working buffers in a static device array of BM3D_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, held from the library's first use on that GPU until the
+ * process ends, instead of params->workspace (ignored).  An image whose
+ * bm3d_workspace_size exceeds it (about 1 MP grey, 0.6 MP colour) gets
+ * BM3D_ERR_UNSUPPORTED, invalid arguments BM3D_ERR_ARG, and nothing is
+ * enqueued then.  Allocates nothing, makes no synchronisation.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race, and the caller must order them.  The array
+ * keeps the last call's working buffers. */
+#define BM3D_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bm3d_denoise_noalloc(const uint8_t* img, int h, int w, int c, float sigma, const bm3d_params* params,
+                         float* out, bm3d_stream_t stream);
+
 /* ---- NL-means: the paper's alternative non-local first stage ----
  * The NLM-G column of Table 3 and the "Ours-FL (NLM)" results (Section III)
  * use NL-means in place of BM3D; the paper cites the pixelwise NL-means of

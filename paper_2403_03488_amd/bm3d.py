@@ -102,6 +102,7 @@ _SIGS = {
     "bm3d_aggregate": (_i, [_vp, _vp, _i, _i, _i, _i, _PP, _vp, _vp]),
     "bm3d_luminance": (_i, [_vp, _i, _i, _i, _vp, _vp]),
     "bm3d_denoise": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
+    "bm3d_denoise_noalloc": (_i, [_vp, _i, _i, _i, _f, _PP, _vp, _vp]),
     "bm3d_nlm_params_default": (_i, [_f, _i, ctypes.POINTER(NlmParams)]),
     "bm3d_nlm": (_i, [_vp, _i, _i, _i, _f, ctypes.POINTER(NlmParams), _vp, _vp]),
     "bm3d_nlm_batch": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, _i, _i, _i, _f,
@@ -310,6 +311,25 @@ def denoise(img, sigma: float, p: Params | None = None, out=None, workspace=None
     _check(_lib.bm3d_denoise(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma),
                              ctypes.byref(p), _ptr(out, torch.float32, "out", h * w * c, True), _stream(stream)),
            "bm3d_denoise")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def denoise_noalloc(img, sigma: float, p: Params | None = None, out=None, stream=None):
+    """bm3d_denoise_noalloc: the two-step denoiser with the library's static
+    device scratch as workspace (no allocation by the library; calls on one
+    GPU must not overlap).  `out` must be given by callers that cannot
+    allocate; otherwise a float32 tensor is made here."""
+    torch = _torch()
+    h, w, c = _hwc(img)
+    p = p or params_default(sigma)
+    if out is None:
+        out = torch.empty(img.shape, dtype=torch.float32, device=img.device)
+    _check(_lib.bm3d_denoise_noalloc(_ptr(img, torch.uint8, "img"), h, w, c, float(sigma), ctypes.byref(p),
+                                     _ptr(out, torch.float32, "out", h * w * c, True), _stream(stream)),
+           "bm3d_denoise_noalloc")
     return out
 
 

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbm3d_mi355x.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bm3d_kernels.hip", "bm3d_api.hip", "nlm.hip", "cnn.hip", "unet.hip", "vst.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bm3d_kernels.hip", "bm3d_api.hip", "bm3d_noalloc.hip", "nlm.hip", "cnn.hip", "unet.hip",
+                                                  "vst.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
