@@ -167,8 +167,10 @@ int bm3d_block_match(const void* src, int src_is_f32, int h, int w, int step,
  * empirical Wiener shrinkage W = B^2/(B^2+sigma^2) of the noisy spectrum, B
  * the spectrum of `basic` (device planar float) over the same patches, weight
  * 1/max(sum W^2, 2^-10).  Weights are per channel.  Each filtered patch at
- * top-left (y0, x0) adds w*K(u)*K(v)*value into num[y0+u][x0+v] (K = Kaiser
- * window of p->kaiser_beta) and w into wsum[y0][x0].
+ * top-left (y0, x0) adds w*K(u)*K(v)*(value - m) into num[y0+u][x0+v] (K =
+ * Kaiser window of p->kaiser_beta; m the channel's centre: 128 for grey,
+ * 128*sqrt3, 0, 0 for the opponent channels -- an exact shift that keeps the
+ * sums small, added back by bm3d_aggregate) and w into wsum[y0][x0].
  * Departure from a per-pixel denominator output: the method's aggregation
  * denominator, the sum of w*K(u)*K(v) over the patches covering a pixel, is
  * the same sum regrouped as wsum correlated with the 8x8 Kaiser window;
@@ -178,8 +180,9 @@ int bm3d_collab_filter(const float* noisy, const float* basic, int h, int w, int
                        float sigma, int step, const int32_t* idx, const int32_t* cnt,
                        const bm3d_params* p, int64_t* num, int64_t* wsum, bm3d_stream_t stream);
 
-/* Aggregation of the BM3D first stage (Fig. 1, Section II): out = num/den
- * with den[y][x] = sum over u,v in 0..7 (y-u, x-v >= 0) of
+/* Aggregation of the BM3D first stage (Fig. 1, Section II): out = num/den + m
+ * (m the channel centre of bm3d_collab_filter), with
+ * den[y][x] = sum over u,v in 0..7 (y-u, x-v >= 0) of
  * wsum[y-u][x-v]*K(u)*K(v), K the Kaiser window of p->kaiser_beta (only that
  * field of p is used; p must still pass validation); num/wsum as written by
  * bm3d_collab_filter.  final_step = 0: out is device planar float

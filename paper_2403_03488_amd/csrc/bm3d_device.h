@@ -106,8 +106,14 @@ constexpr int kNumFrac = 28, kWsumFrac = 40;
 // whose pilot spectrum is all but zero filters to ~0 whatever its weight);
 // step-1 weights are at most 1.
 constexpr float kMaxWeight = 1024.f;
+// Rounding to the nearest integer by the double-precision magic number
+// 1.5 * 2^52: for |v 2^FRAC| < 2^51 the sum keeps the rounded value in its
+// low mantissa bits, read out by an integer subtraction (4 instructions
+// instead of a generic float-to-int64 conversion).
 template <int FRAC> __device__ inline int64_t to_fix(float v) {
-  return (int64_t)__builtin_rint((double)v * (double)(1ull << FRAC));
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  const double t = __builtin_fma((double)v, (double)(1ull << FRAC), magic);
+  return __double_as_longlong(t) - __double_as_longlong(magic);
 }
 template <int FRAC> __device__ inline float from_fix(int64_t n) {
   return (float)((double)n * (1.0 / (double)(1ull << FRAC)));
@@ -116,6 +122,19 @@ template <int FRAC> __device__ inline void gadd_fix(int64_t* p, float v) {
   __hip_atomic_fetch_add((BM3D_GLOBAL unsigned long long*)p, (unsigned long long)to_fix<FRAC>(v),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ inline void gadd_i64(int64_t* p, int64_t v) {
+  __hip_atomic_fetch_add((BM3D_GLOBAL unsigned long long*)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+// LDS integer atomics (ds_add_u64, no return) are fast on gfx950 -- a few
+// clocks per wave instruction, against ~190 for ds_add_f32 -- which is what
+// makes exact fixed-point accumulation in LDS cheap.
+#define BM3D_LDS __attribute__((address_space(3)))
+__device__ inline void lds_add_i64(int64_t* p, int64_t v) {
+  __hip_atomic_fetch_add((BM3D_LDS unsigned long long*)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 
 // ----------------------------------------------------- wave primitives ---
 __device__ inline int lane_id() { return __lane_id(); }

@@ -89,6 +89,7 @@ __device__ void agg_channel(const ImgDesc& d, const KParams& kp, int ch, int y0,
   const size_t hw = (size_t)d.h * d.w;
   const int64_t* __restrict__ ws = d.wsum + ch * hw;
   const int tid = threadIdx.x, xx = tid & 63, wv = tid >> 6;
+  const float centre = channel_centre(d.c, ch);
   for (int i = tid; i < (kAggRows + 7) * (kAggCols + 8); i += kThreads) {
     const int r = i / (kAggCols + 8), cc = i - r * (kAggCols + 8);
     const int y = y0 - 7 + r, x = x0 - 8 + cc;
@@ -108,7 +109,8 @@ __device__ void agg_channel(const ImgDesc& d, const KParams& kp, int ch, int y0,
     float den = 0.f;
 #pragma unroll
     for (int u = 0; u < 8; u++) den = __builtin_fmaf(kp.kaiser[u], sh.hs[yl + 7 - u][xx], den);
-    e[k] = (y < d.h && x < d.w) ? from_fix<kNumFrac>(d.num[ch * hw + (size_t)y * d.w + x]) / den : 0.f;
+    // the filters accumulate values relative to the channel centre
+    e[k] = (y < d.h && x < d.w) ? from_fix<kNumFrac>(d.num[ch * hw + (size_t)y * d.w + x]) / den + centre : 0.f;
   }
   __syncthreads();  // the LDS is reused by the next channel / item
 }
@@ -600,42 +602,47 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
 //   D4[pix][g]    = sum_coef CC^T[pix][coef] D3[coef][g]     inverse 2-D DCT
 // Each product's accumulator feeds the next one without data movement.
 //
-// Aggregation without atomics.  Within a wave, accumulator pixel (y, x) is
-// only ever updated by lane (y mod 8)*8 + (x mod 8): an 8x8 member patch
-// covers every residue exactly once, so one 64-lane step adds a whole member
-// at 64 distinct addresses, and all contributions to one pixel come from one
-// lane in program order.  Filtered patches reach their owning lanes through a
-// small per-wave staging buffer, four members per step (coinciding addresses
-// within a step are merged in registers).  The denominator sum of w K(u)K(v)
-// over member placements equals the Kaiser window correlated with the
-// per-position sum of group weights, so the filter adds each member's weight
-// once, at its corner, into a global weight map (wsum); the aggregation forms
-// the denominator from it.  Keeping no weight map in LDS leaves room for
-// 8 waves per CU with 16-bit operands (6 with FP32 operands, whose DCT
-// tables are twice as large).
+// Exact aggregation in LDS.  The wave's region accumulates signed 64-bit
+// fixed point (kNumFrac fractional bits) with LDS integer atomics: straight
+// from the inverse DCT's accumulator layout, lane (q, member m) adds its 16
+// pixels of member m at one base address plus immediate offsets, with no
+// transposition and no ordering between members (integer additions are
+// exact and commute).  The region is then added into num with one global
+// 64-bit atomic per touched pixel, with no conversion.  Filtered values are
+// accumulated relative to the channel centre (bm3d_aggregate adds it back
+// as centre * den), which keeps the sums small.  The denominator sum of
+// w K(u)K(v) over member placements equals the Kaiser window correlated with
+// the per-position sum of group weights, so the filter adds each member's
+// weight once, at its corner, into a global weight map (wsum); the
+// aggregation forms the denominator from it.
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
-  static constexpr int kWaves = sizeof(frag) == 16 ? 6 : 8;  // waves per workgroup
-  // staging row pitch: member rows 68 floats apart, so the 16 lanes of a
-  // fragment row write to different LDS banks
-  static constexpr int kSP = 68;
+  static constexpr int kMaxWaves = 8;  // waves per workgroup at most
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag) + 64 * 4; }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
-  // row pitch of the numerator region: = 8 (mod 16) so the 8 rows of a
-  // member patch fall in different LDS banks
-  static __host__ __device__ int pitch(int rw) { return rw + ((24 - rw % 16) % 16); }
-  // numerator region, staging [16][kSP], one spare slot per lane
+  // region row pitch in 64-bit words: odd, so the rows of a member patch
+  // spread over the LDS banks
+  static __host__ __device__ int pitch(int rw) { return rw | 1; }
   static __host__ __device__ size_t per_wave(int S, int T) {
-    return ((size_t)rnum(S, T) * pitch(rnum(S, T)) + 16 * kSP + 64) * 4;
+    return (size_t)rnum(S, T) * pitch(rnum(S, T)) * sizeof(int64_t);
   }
-  static __host__ __device__ size_t bytes(int S, int T) { return tables() + kWaves * per_wave(S, T); }
+  // waves per workgroup: as many as the LDS holds (0: the tile does not fit)
+  static __host__ __device__ int waves(int S, int T) {
+    const size_t t = tables(), pw = per_wave(S, T);
+    const size_t n = t >= kLdsBytes ? 0 : (kLdsBytes - t) / pw;
+    return n > (size_t)kMaxWaves ? kMaxWaves : (int)n;
+  }
+  static __host__ __device__ size_t bytes(int S, int T) {
+    const int nw = waves(S, T);
+    return nw == 0 ? kLdsBytes + 1 : tables() + (size_t)nw * per_wave(S, T);
+  }
 };
 
 __host__ __device__ inline size_t filter_lds_bytes(int xform, int S, int T) {
   return xform == 0 ? FilterCfg<XF32>::bytes(S, T) : FilterCfg<XBF16>::bytes(S, T);
 }
-__host__ __device__ inline int filter_waves(int xform) {
-  return xform == 0 ? FilterCfg<XF32>::kWaves : FilterCfg<XBF16>::kWaves;
+__host__ __device__ inline int filter_waves(int xform, int S, int T) {
+  return xform == 0 ? FilterCfg<XF32>::waves(S, T) : FilterCfg<XBF16>::waves(S, T);
 }
 
 // Hadamard entry (+-1) of the n-point Sylvester matrix, 0 outside n x n.
@@ -698,7 +705,7 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
 template <int STEP, class XF>
 __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
                                  const typename XF::frag* __restrict__ tabB,
-                                 const typename XF::frag* __restrict__ tabA, float* wnum) {
+                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
   const int S = STEP == 1 ? kp.S1 : kp.S2;
@@ -712,11 +719,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const int q = l >> 4, col = l & 15;
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, T, ty, tx);
   const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
-  const int RP = C::pitch(RW);             // its row pitch
-  float* wst = wnum + C::rnum(S, T) * C::pitch(C::rnum(S, T));  // staging [16][kSP]
+  const int RP = C::pitch(RW);             // its row pitch (64-bit words)
   int64_t* __restrict__ gwsum = d.wsum + ch * hw;
 
-  for (int i = l; i < RH * RP; i += 64) wnum[i] = 0.f;
+  for (int i = l; i < RH * RP; i += 64) wreg[i] = 0;
   wave_lds_sync();
 
   const float centre = channel_centre(d.c, ch);
@@ -725,25 +731,6 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   const float sig2 = d.sigma * d.sigma;
   const float thr = d.lam_sigma;
   const float inv_w = 1.f / (float)w;
-  // Kaiser weight of the pixels this lane holds in an inverse-DCT
-  // fragment: Ku[mt] (row factor) times Kv[v] (column factor)
-  float Ku[4], Kv[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    Ku[i] = kp.kaiser[2 * i + (q >> 1)];
-    Kv[i] = kp.kaiser[4 * (q & 1) + i];
-  }
-  // the lane owns accumulator residue (ru, rv); for a patch whose corner has
-  // phase s (mod 8) the owned pixel sits at patch row (ru - s) & 7, packed
-  // here in 3-bit fields for s = 0..7 (same for columns)
-  const int ru = l >> 3, rv = l & 7;
-  uint32_t Upk = 0, Vpk = 0;
-#pragma unroll
-  for (int s = 0; s < 8; s++) {
-    Upk |= (uint32_t)((ru - s) & 7) << (3 * s);
-    Vpk |= (uint32_t)((rv - s) & 7) << (3 * s);
-  }
-
   frag Hf[2][2];  // Hadamard blocks of the current group size
   int hn = 0;
   const int nrefs = g.nri * g.nci;
@@ -753,10 +740,23 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   // aggregated (slots beyond the group hold -1 and are ignored below).  Step
   // 2 loads its pixels when it uses them: holding them across the
   // aggregation would spill registers there.
-  auto ref_of = [&](int j) { return (size_t)(g.ri0 + j / g.nci) * d.nc + g.ci0 + j % g.nci; };
+  // The tile's references in row-major order, by global index: walked with
+  // counters (an integer division on the scalar unit costs tens of
+  // instructions).  One walk for the prefetch, one for the current reference.
+  size_t r_pf = (size_t)g.ri0 * d.nc + g.ci0, r_cur = r_pf;
+  int c_pf = 0, c_cur = 0;
+  auto advance = [&](size_t& r, int& c) {
+    if (++c == g.nci) {
+      c = 0;
+      r += d.nc - g.nci + 1;
+    } else {
+      r++;
+    }
+  };
   int cnt_nx = 0, gi_nx[2] = {-1, -1};
-  auto prefetch = [&](int j) {
-    const size_t rn = ref_of(j);
+  auto prefetch = [&]() {  // the next reference not yet prefetched
+    const size_t rn = r_pf;
+    advance(r_pf, c_pf);
     cnt_nx = ldg(cnt + rn);
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) gi_nx[gt] = ldg(idx + rn * nmax + (16 * gt + col < nmax ? 16 * gt + col : 0));
@@ -794,12 +794,13 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     }
   };
   if (nrefs > 0) {
-    prefetch(0);
+    prefetch();
     stage();
-    if (nrefs > 1) prefetch(1);
+    if (nrefs > 1) prefetch();
   }
   for (int j = 0; j < nrefs; j++) {
-    const size_t r = ref_of(j);
+    const size_t r = r_cur;
+    advance(r_cur, c_cur);
     // the group size and everything derived from it are wave-uniform (kept
     // in scalar registers: the transforms branch on them)
     const int n = __builtin_amdgcn_readfirstlane(n_nx);
@@ -941,12 +942,9 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     if (l == 0) D2[0][0][0] -= off;
 
     // ---- inverse WHT, with this lane's member weight (0 if absent) folded in
-    float wm[2], cw[2];
+    float wm[2];
 #pragma unroll
-    for (int gt = 0; gt < 2; gt++) {
-      wm[gt] = mv[gt] ? wgt : 0.f;
-      cw[gt] = wm[gt] * centre;
-    }
+    for (int gt = 0; gt < 2; gt++) wm[gt] = mv[gt] ? wgt : 0.f;
     f32x4 D3[4][2];
 #pragma unroll
     for (int ct = 0; ct < 4; ct++) {
@@ -961,15 +959,20 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     // the next reference's positions and noisy pixels, then slots two ahead
     if (j + 1 < nrefs) {
       stage();
-      if (j + 2 < nrefs) prefetch(j + 2);
+      if (j + 2 < nrefs) prefetch();
     }
-    // ---- inverse 2-D DCT, Kaiser weighting, aggregation (wave-private LDS)
+    // ---- inverse 2-D DCT (the Kaiser weight of each output pixel is folded
+    // into the table), exact accumulation into the wave's region.  Lane
+    // (q, col) holds pixels (2 mt + q/2, 4 (q&1) + v) of member 16 gt + col:
+    // one base address per lane, the rest immediate offsets.  An absent
+    // member has weight 0 and a valid (corner) position.
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) {
       if (gt >= NG) break;
       frag b3[4];
 #pragma unroll
       for (int ct = 0; ct < 4; ct++) b3[ct] = XF::cvt(D3[ct][gt]);
+      int64_t* rb = wreg + (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
 #pragma unroll
       for (int mt = 0; mt < 4; mt++) {
         f32x4 acc = zero4();
@@ -978,70 +981,35 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
           const frag* ta = tabA + ((mt * 2 + c2) * 64 + l) * 2;
           acc = XF::mma2(ta[0], ta[1], b3[2 * c2], b3[2 * c2 + 1], acc);
         }
-        // acc already holds K(pixel) times the filtered value; the centre
-        // (times the member weight) gets the same Kaiser weight here
-        const float kc = Ku[mt] * cw[gt];
-        f32x4 add;
+        int64_t* rr = rb + 2 * mt * RP;
 #pragma unroll
-        for (int v = 0; v < 4; v++) add[v] = __builtin_fmaf(kc, Kv[v], acc[v]);
-        *(f32x4*)(wst + col * C::kSP + 16 * mt + 4 * q) = add;  // member col, pixels 16mt+4q..+3
+        for (int v = 0; v < 4; v++) lds_add_i64(rr + v, to_fix<kNumFrac>(acc[v]));
       }
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
-      wave_lds_sync();
-      // four members per step (an absent member stages zeros at the region
-      // corner); the writes go in member order, so where members coincide
-      // on this lane's pixel the last write carries every contribution
-      const int packed = mv[gt] ? (((my[gt] - g.uy0) << 16) | (mx[gt] - g.ux0)) : 0;
-#pragma unroll
-      for (int mb = 0; mb < 16; mb += 4) {
-        if (16 * gt + mb >= n) break;
-        int a[4];
-        float sv[4], o[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int pk = __builtin_amdgcn_readlane(packed, mb + i);
-          const int py = pk >> 16, px = pk & 0xffff;
-          const int u = (Upk >> (3 * (py & 7))) & 7, v = (Vpk >> (3 * (px & 7))) & 7;
-          a[i] = (int)__umul24((unsigned)u, (unsigned)RP) + v + (py * RP + px);
-          sv[i] = wst[(mb + i) * C::kSP + u * 8 + v];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; i++) o[i] = wnum[a[i]];
-        // a member coinciding with earlier ones of the step continues from
-        // the latest of their new values
-        float t[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          float base = o[i];
-#pragma unroll
-          for (int k = 0; k < i; k++) base = a[k] == a[i] ? t[k] : base;
-          t[i] = base + sv[i];
-          wnum[a[i]] = t[i];
-        }
-      }
-      wave_lds_sync();
     }
   }
 
   // ---- flush: the region into num, four rows per iteration (all their LDS
   // reads first); pixels no member touched hold exact zeros and are skipped
+  wave_lds_sync();
   int64_t* gnum = d.num + ch * hw;
   for (int x0 = 0; x0 < RW; x0 += 64) {
     const int x = x0 + l;
     const int xc = min(x, RW - 1);  // in-range address for lanes past the region
     for (int y0 = 0; y0 < RH; y0 += 4) {
-      float nv[4];
+      int64_t nv[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) nv[k] = wnum[min(y0 + k, RH - 1) * RP + xc];
+      for (int k = 0; k < 4; k++) nv[k] = wreg[min(y0 + k, RH - 1) * RP + xc];
 #pragma unroll
       for (int k = 0; k < 4; k++)
-        if (y0 + k < RH && x < RW && nv[k] != 0.f) gadd_fix<kNumFrac>(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
+        if (y0 + k < RH && x < RW && nv[k] != 0) gadd_i64(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
     }
   }
   wave_lds_sync();
 }
 
-// One workgroup = kWaves waves, each on its own reference tile.
+// One workgroup = as many waves as the LDS holds (blockDim.x / 64), each on
+// its own reference tile.
 template <int STEP, class XF>
 __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch, char* smem) {
   typedef typename XF::frag frag;
@@ -1052,11 +1020,11 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
-  const int wave = threadIdx.x >> 6;
-  float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t* wreg = (int64_t*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
   const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
-  const int t = blockIdx.x * C::kWaves + wave;
-  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wnum);
+  const int t = blockIdx.x * nw + wave;
+  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg);
 }
 
 // image holding global item i: largest k with prefix[k] <= i
@@ -1082,18 +1050,17 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   // the work index is wave-uniform, so the descriptor below is read once
   // with scalar loads and kept in registers (a reference into global memory
   // would be re-read after every store the compiler cannot disambiguate)
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float* wnum = (float*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  int64_t* wreg = (int64_t*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
   // With a counter, tiles go to waves as they become free (tile costs vary
   // with group sizes and image edges, and a workgroup holds its LDS until
   // its last wave ends); one atomic per tile, against the tile's ~10^5
   // cycles, all lanes taking part with lane 0 adding 1.  Without one, wave w
-  // of workgroup b takes every (gridDim.x * kWaves)-th tile from
-  // b * kWaves + w.
+  // of workgroup b takes every (gridDim.x * nw)-th tile from b * nw + w.
   const int l = lane_id();
   const bool dyn = br.ctr != nullptr;
-  const int total = br.end - br.begin, stride = gridDim.x * C::kWaves;
-  int t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : blockIdx.x * C::kWaves + wave);
+  const int total = br.end - br.begin, stride = gridDim.x * nw;
+  int t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : blockIdx.x * nw + wave);
   while (t < total) {
     const int i = br.begin + t;
     const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
@@ -1101,12 +1068,12 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
-    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wnum);
+    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg);
     t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : t + stride);
   }
   // every wave has drawn an index past the end; the last one to get here
   // zeroes the pair for the next launch
-  if (dyn && l == 0 && atomicAdd(br.ctr + 1, 1) == (int)gridDim.x * C::kWaves - 1) {
+  if (dyn && l == 0 && atomicAdd(br.ctr + 1, 1) == (int)gridDim.x * nw - 1) {
     atomicExch(br.ctr, 0);
     atomicExch(br.ctr + 1, 0);
   }
@@ -1133,7 +1100,7 @@ __global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
   match2_block(d, kp, blockIdx.y, blockIdx.x, smem);
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) k_filter(ImgDesc d, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kMaxWaves) k_filter(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
 }
@@ -1166,7 +1133,7 @@ __global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
   }
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) kb_filter(BatchRef br, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kMaxWaves) kb_filter(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_batch<STEP, XF>(br, kp, smem);
 }
@@ -1221,7 +1188,8 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
     case STAGE_FILTER1:
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
-      const int nw = filter_waves(xform);
+      const int nw = filter_waves(xform, S, kp.tile);
+      if (nw < 1) return -1;
       const int ntiles = ((d.nc + kp.tile - 1) / kp.tile) * ((d.nr + kp.tile - 1) / kp.tile);
       dim3 grid((ntiles + nw - 1) / nw, d.c);
       size_t b = filter_lds_bytes(xform, S, kp.tile);
@@ -1274,7 +1242,8 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
     case STAGE_FILTER1:
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
-      const int wv = filter_waves(xform);
+      const int wv = filter_waves(xform, S, kp.tile);
+      if (wv < 1) return -1;
       size_t b = filter_lds_bytes(xform, S, kp.tile);
       int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
       // dynamic tiles: as many workgroups as fit on the device at once
@@ -1310,6 +1279,5 @@ size_t stage_lds_bytes(int stage, int xform, const KParams& kp) {
 }
 
 int elem_chunk() { return kChunk; }
-int filter_block_waves(int xform) { return filter_waves(xform); }
 
 }  // namespace bm3d

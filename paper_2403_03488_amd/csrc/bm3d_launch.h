@@ -63,6 +63,5 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
                  bool sync, int cus = 0);
 size_t stage_lds_bytes(int stage, int xform, const KParams& kp);
 int elem_chunk();
-int filter_block_waves(int xform);
 
 }  // namespace bm3d

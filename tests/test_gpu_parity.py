@@ -248,13 +248,17 @@ def test_aggregate(B, c):
     gnum, gws = dev(num), dev(wsum)
     out = torch.empty((33, 147, c) if c == 3 else (c, 33, 147), dtype=torch.float32, device="cuda")
     B.aggregate(gnum, gws, True, p, out)
-    ref = oracle.aggregate(ph.from_fix(num, "num"), den, True)
+    # num holds the weighted values relative to the channel centre (128 grey;
+    # 128 sqrt3, 0, 0 for the opponent channels): the real numerator adds
+    # centre * den back
+    centre = np.array([128.0] if c == 1 else [128.0 * np.sqrt(3.0), 0.0, 0.0])[:, None, None]
+    real_num = ph.from_fix(num, "num") + centre * den
+    ref = oracle.aggregate(real_num, den, True)
     # FP32 denominator (two 8-term FMA chains) and division: relative error ~1e-6
     np.testing.assert_allclose(host(out).reshape(ref.shape), ref, rtol=1e-5, atol=1e-4)
     basic = torch.empty((c, 33, 147), dtype=torch.float32, device="cuda")
     B.aggregate(gnum, gws, False, p, basic)
-    np.testing.assert_allclose(host(basic), oracle.aggregate(ph.from_fix(num, "num"), den, False),
-                               rtol=1e-5, atol=1e-4)
+    np.testing.assert_allclose(host(basic), oracle.aggregate(real_num, den, False), rtol=1e-5, atol=1e-4)
     lum = torch.empty((33, 147), dtype=torch.float32, device="cuda")
     B.luminance(basic, lum)
     np.testing.assert_allclose(host(lum), oracle.luminance(host(basic).astype(np.float64)), atol=1e-4)
