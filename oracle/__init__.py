@@ -50,6 +50,10 @@ def lib():
         L.orc_kaiser.argtypes = [cd, f64p]
         L.orc_opponent.argtypes = [f64p]
         L.orc_transform3d.argtypes = [f64p, ci, f64p, ci]
+        L.orc_transform3d_ex.argtypes = [f64p, ci, f64p, ci, ci]
+        L.orc_bior15_filters.argtypes = [f64p]
+        L.orc_bior15_matrix.argtypes = [f64p, f64p]
+        L.orc_match_prefiltered.argtypes = [u8p, ci, ci, ci, ci, cd, cd, ci, i32p, i32p]
         L.orc_prepare.argtypes = [u8p, ci, ci, ci, f64p, u8p]
         L.orc_match_u8.argtypes = [u8p, ci, ci, ci, ci, cd, i32p, i32p]
         L.orc_match_f64.argtypes = [f64p, ci, ci, ci, ci, cd, i32p, i32p]
@@ -69,7 +73,11 @@ class _CParams(ctypes.Structure):
     _fields_ = [("search_ht", ctypes.c_int), ("search_wie", ctypes.c_int),
                 ("n_ht", ctypes.c_int), ("n_wie", ctypes.c_int),
                 ("lambda_ht", ctypes.c_double), ("tau_ht", ctypes.c_double),
-                ("tau_wie", ctypes.c_double), ("kaiser_beta", ctypes.c_double)]
+                ("tau_wie", ctypes.c_double), ("kaiser_beta", ctypes.c_double),
+                ("transform_ht", ctypes.c_int), ("lambda_2d", ctypes.c_double)]
+
+
+T_DCT, T_BIOR15 = 0, 1  # step-1 2-D transforms
 
 
 @dataclass
@@ -84,6 +92,8 @@ class Params:
     tau_ht: float = 2500.0
     tau_wie: float = 400.0
     kaiser_beta: float = 2.0
+    transform_ht: int = 0     # step-1 2-D transform: T_DCT or T_BIOR15
+    lambda_2d: float = 0.0    # > 0: prefiltered step-1 matching (high-noise profile)
 
     @staticmethod
     def for_sigma(sigma: float, search: int = 32) -> "Params":
@@ -94,7 +104,8 @@ class Params:
 
     def _c(self):
         return _CParams(self.search_ht, self.search_wie, self.n_ht, self.n_wie,
-                        self.lambda_ht, self.tau_ht, self.tau_wie, self.kaiser_beta)
+                        self.lambda_ht, self.tau_ht, self.tau_wie, self.kaiser_beta,
+                        self.transform_ht, self.lambda_2d)
 
 
 def set_threads(n: int):
@@ -140,12 +151,39 @@ def opponent() -> np.ndarray:
     return t.reshape(3, 3)
 
 
-def transform3d(group: np.ndarray, inverse: bool = False) -> np.ndarray:
+def transform3d(group: np.ndarray, inverse: bool = False, transform: int = T_DCT) -> np.ndarray:
     g = np.ascontiguousarray(group, np.float64)
     n = g.shape[0]
     s = np.zeros_like(g)
-    lib().orc_transform3d(g.reshape(-1), n, s.reshape(-1), 1 if inverse else 0)
+    lib().orc_transform3d_ex(g.reshape(-1), n, s.reshape(-1), 1 if inverse else 0, int(transform))
     return s
+
+
+def bior15_filters() -> np.ndarray:
+    """bior1.5 analysis lowpass taps at offsets -4..5."""
+    lo = np.zeros(10)
+    lib().orc_bior15_filters(lo)
+    return lo
+
+
+def bior15_matrix():
+    """(F, I): the 8-point bior1.5 forward matrix F[a, u] (unit-norm rows)
+    and its inverse I[u, a]."""
+    f, i = np.zeros(64), np.zeros(64)
+    lib().orc_bior15_matrix(f, i)
+    return f.reshape(8, 8), i.reshape(8, 8)
+
+
+def match_prefiltered(lum, search: int, nmax: int, tau: float, thr2d: float, transform: int = T_DCT):
+    """Step-1 grouping on 2-D spectra hard-thresholded at thr2d."""
+    lum = np.ascontiguousarray(lum, np.uint8)
+    h, w = lum.shape
+    R = num_refs(h, w)
+    idx = np.zeros((R, nmax), np.int32)
+    cnt = np.zeros(R, np.int32)
+    lib().orc_match_prefiltered(lum.reshape(-1), h, w, search, nmax, tau, thr2d, int(transform),
+                                idx.reshape(-1), cnt)
+    return idx, cnt
 
 
 def _img_hwc(img):

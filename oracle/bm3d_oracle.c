@@ -112,12 +112,110 @@ void orc_opponent(double* t) {
   memcpy(t, m, sizeof m);
 }
 
+/* ---------------------------------------------------- bior1.5 (variant) --- */
+
+/* The biorthogonal spline wavelet bior1.5 (Cohen, Daubechies, Feauveau; the
+ * step-1 2-D transform of the published BM3D): a box synthesis scaling
+ * function, so the analysis highpass is the Haar difference, and an
+ * analysis lowpass of 10 taps, symmetric about 1/2, with five zeros at pi
+ * (values of the published table, sqrt2/256 * integers). */
+static const double kBiorLo[10] = {3.0, -3.0, -22.0, 22.0, 128.0, 128.0, 22.0, -22.0, -3.0, 3.0};
+
+void orc_bior15_filters(double* lo10) {
+  for (int i = 0; i < 10; i++) lo10[i] = kBiorLo[i] * sqrt(2.0) / 256.0;
+}
+
+/* One analysis level of a periodic signal x of even length m:
+ * a[k] = sum_{j=-4..5} lo[j] x[(2k+j) mod m], d[k] = (x[2k] - x[2k+1]) / sqrt2. */
+static void bior_level(const double* x, int m, double* a, double* d) {
+  double lo[10];
+  orc_bior15_filters(lo);
+  for (int k = 0; k < m / 2; k++) {
+    double s = 0.0;
+    for (int j = -4; j <= 5; j++) s += lo[j + 4] * x[(((2 * k + j) % m) + m) % m];
+    a[k] = s;
+    d[k] = (x[2 * k] - x[2 * k + 1]) / sqrt(2.0);
+  }
+}
+
+/* Inverse of an 8x8 matrix by Gauss-Jordan elimination with partial pivoting. */
+static void invert8(const double* a, double* inv) {
+  double m[8][16];
+  for (int i = 0; i < 8; i++)
+    for (int j = 0; j < 16; j++) m[i][j] = j < 8 ? a[i * 8 + j] : (j - 8 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 8; c++) {
+    int piv = c;
+    for (int r = c + 1; r < 8; r++)
+      if (fabs(m[r][c]) > fabs(m[piv][c])) piv = r;
+    for (int j = 0; j < 16; j++) {
+      double t = m[c][j];
+      m[c][j] = m[piv][j];
+      m[piv][j] = t;
+    }
+    double p = m[c][c];
+    for (int j = 0; j < 16; j++) m[c][j] /= p;
+    for (int r = 0; r < 8; r++) {
+      if (r == c) continue;
+      double f = m[r][c];
+      for (int j = 0; j < 16; j++) m[r][j] -= f * m[c][j];
+    }
+  }
+  for (int i = 0; i < 8; i++)
+    for (int j = 0; j < 8; j++) inv[i * 8 + j] = m[i][8 + j];
+}
+
+/* 8-point bior1.5 transform with full dyadic decomposition: three analysis
+ * levels (8 -> 4 -> 2 -> 1 samples) on the periodic extension, coefficients
+ * ordered coarse to fine [a3, d3, d2[0..1], d1[0..3]].  Each row of the
+ * forward matrix F[a][u] is normalised to unit norm, so white noise of
+ * level sigma gives coefficients of level sigma; the inverse is the matrix
+ * inverse, stored I[u][a]. */
+void orc_bior15_matrix(double* fwd, double* inv) {
+  double F[64];
+  for (int u = 0; u < P; u++) {
+    double x[8] = {0}, a1[4], d1[4], a2[2], d2[2], a3[1], d3[1];
+    x[u] = 1.0;
+    bior_level(x, 8, a1, d1);
+    bior_level(a1, 4, a2, d2);
+    bior_level(a2, 2, a3, d3);
+    double col[8] = {a3[0], d3[0], d2[0], d2[1], d1[0], d1[1], d1[2], d1[3]};
+    for (int a = 0; a < P; a++) F[a * P + u] = col[a];
+  }
+  for (int a = 0; a < P; a++) {
+    double nrm = 0.0;
+    for (int u = 0; u < P; u++) nrm += F[a * P + u] * F[a * P + u];
+    nrm = sqrt(nrm);
+    for (int u = 0; u < P; u++) F[a * P + u] /= nrm;
+  }
+  if (fwd) memcpy(fwd, F, sizeof F);
+  if (inv) invert8(F, inv);
+}
+
+/* The 8-point forward matrix F[a][u] and inverse I[u][a] of a step-1 2-D
+ * transform (separable: the same along rows and columns). */
+static void transform_pair(int transform, double* F, double* I) {
+  if (transform == ORC_T_BIOR15) {
+    orc_bior15_matrix(F, I);
+    return;
+  }
+  orc_dct_matrix(F);
+  for (int a = 0; a < P; a++)
+    for (int u = 0; u < P; u++) I[u * P + a] = F[a * P + u];  /* orthonormal: the transpose */
+}
+
 /* 3D transform of a group g[n][8][8]: 2D DCT of each patch, then the
  * normalised Walsh-Hadamard transform along the group axis.  inverse!=0
  * applies the transposes in reverse order. */
 void orc_transform3d(const double* g, int n, double* s, int inverse) {
-  double C[64];
-  orc_dct_matrix(C);
+  orc_transform3d_ex(g, n, s, inverse, ORC_T_DCT);
+}
+
+/* As orc_transform3d with the given 2-D transform: forward F along rows and
+ * columns of every patch, then the Walsh-Hadamard transform; the inverse
+ * undoes the Walsh-Hadamard transform, then applies I along both axes. */
+void orc_transform3d_ex(const double* g, int n, double* s, int inverse, int transform) {
+  double C[64], Ci[64];
+  transform_pair(transform, C, Ci);
   double* H = (double*)malloc(sizeof(double) * n * n);
   double* t1 = (double*)malloc(sizeof(double) * n * 64);
   double* t2 = (double*)malloc(sizeof(double) * n * 64);
@@ -156,14 +254,14 @@ void orc_transform3d(const double* g, int n, double* s, int inverse) {
       for (int u = 0; u < P; u++)
         for (int b = 0; b < P; b++) {
           double acc = 0.0;
-          for (int a = 0; a < P; a++) acc += C[a * P + u] * t1[m * 64 + a * P + b];
+          for (int a = 0; a < P; a++) acc += Ci[u * P + a] * t1[m * 64 + a * P + b];
           t2[m * 64 + u * P + b] = acc;
         }
     for (int m = 0; m < n; m++)
       for (int u = 0; u < P; u++)
         for (int v = 0; v < P; v++) {
           double acc = 0.0;
-          for (int b = 0; b < P; b++) acc += C[b * P + v] * t2[m * 64 + u * P + b];
+          for (int b = 0; b < P; b++) acc += Ci[v * P + b] * t2[m * 64 + u * P + b];
           s[m * 64 + u * P + v] = acc;
         }
   }
@@ -285,6 +383,43 @@ void orc_match_f64(const double* lum, int h, int w, int S, int nmax, double tau,
   })
 }
 
+/* Step-1 grouping of the high-noise profile: every 8x8 patch of the
+ * matching luminance is taken to its 2-D spectrum (the step-1 transform),
+ * coefficients with |c| <= thr2d are set to zero, and the distance of two
+ * patches is the squared Euclidean distance of these thresholded spectra;
+ * the rest is orc_match_u8 (within 64 tau, (distance, index) order,
+ * power-of-two size, reference first). */
+void orc_match_prefiltered(const uint8_t* lum, int h, int w, int S, int nmax, double tau,
+                           double thr2d, int transform, int32_t* idx, int32_t* cnt) {
+  const int ph = h - P + 1, pw = w - P + 1;
+  double* co = (double*)malloc(sizeof(double) * (size_t)ph * pw * 64);
+  double F[64], I[64];
+  transform_pair(transform, F, I);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+  for (int y = 0; y < ph; y++)
+    for (int x = 0; x < pw; x++) {
+      double t1[64];
+      double* c = co + ((size_t)y * pw + x) * 64;
+      for (int u = 0; u < P; u++)
+        for (int b = 0; b < P; b++) {
+          double acc = 0.0;
+          for (int v = 0; v < P; v++) acc += F[b * P + v] * lum[(size_t)(y + u) * w + x + v];
+          t1[u * P + b] = acc;
+        }
+      for (int a = 0; a < P; a++)
+        for (int b = 0; b < P; b++) {
+          double acc = 0.0;
+          for (int u = 0; u < P; u++) acc += F[a * P + u] * t1[u * P + b];
+          c[a * P + b] = fabs(acc) > thr2d ? acc : 0.0;
+        }
+    }
+  MATCH_BODY({
+    double e = co[((size_t)ry * pw + rx) * 64 + u * P + v] - co[((size_t)qy * pw + qx) * 64 + u * P + v];
+    d += e * e;
+  })
+  free(co);
+}
+
 /* ------------------------------------------------ collaborative filter --- */
 
 /* Filters every group and accumulates it.  step 1: hard thresholding of the
@@ -332,7 +467,8 @@ void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
               if (step == 2) gb[m * 64 + u * P + v] = basic[o];
             }
         }
-        orc_transform3d(g, n, s, 0);
+        const int xf = step == 1 ? p->transform_ht : ORC_T_DCT;
+        orc_transform3d_ex(g, n, s, 0, xf);
         double weight;
         if (step == 1) {
           int kept = 0;
@@ -362,7 +498,7 @@ void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
            * defined) */
           weight = 1.0 / (sw2 > 0x1p-10 ? sw2 : 0x1p-10);
         }
-        orc_transform3d(s, n, g, 1);
+        orc_transform3d_ex(s, n, g, 1, xf);
         memcpy(est + ((size_t)ci * c + k) * nmax * 64, g, sizeof(double) * n * 64);
         wt[(size_t)ci * c + k] = weight;
       }
@@ -430,7 +566,15 @@ int orc_denoise(const uint8_t* img, int h, int w, int c, double sigma, const orc
   int32_t* c2 = cnt2 ? cnt2 : (int32_t*)malloc(sizeof(int32_t) * R);
 
   orc_prepare(img, h, w, c, planar, lum);
-  orc_match_u8(lum, h, w, p->search_ht, p->n_ht, p->tau_ht, i1, c1);
+  if (p->lambda_2d > 0.0) {
+    /* the matching luminance carries noise sigma (grey) or sigma/sqrt3 (the
+     * mean of three channels) */
+    const double sl = c == 1 ? sigma : sigma / sqrt(3.0);
+    orc_match_prefiltered(lum, h, w, p->search_ht, p->n_ht, p->tau_ht, p->lambda_2d * sl, p->transform_ht,
+                          i1, c1);
+  } else {
+    orc_match_u8(lum, h, w, p->search_ht, p->n_ht, p->tau_ht, i1, c1);
+  }
   orc_filter(planar, NULL, h, w, c, sigma, 1, i1, c1, p->n_ht, p, num, den, NULL, NULL);
   orc_aggregate(num, den, h, w, c, 0, basic);
   if (basic_planar) memcpy(basic_planar, basic, sizeof(double) * c * hw);

@@ -31,7 +31,14 @@ typedef struct {
   double lambda_ht;          /* hard threshold multiplier (2.7) */
   double tau_ht, tau_wie;    /* per-pixel distance thresholds; INFINITY disables */
   double kaiser_beta;        /* 2.0 */
+  /* variants of the published method (high-noise profile) */
+  int transform_ht;          /* step-1 2-D transform: ORC_T_DCT or ORC_T_BIOR15 */
+  double lambda_2d;          /* > 0: step-1 matching on 2-D spectra hard-thresholded at
+                                lambda_2d times the matching signal's noise level */
 } orc_params;
+
+#define ORC_T_DCT 0
+#define ORC_T_BIOR15 1
 
 void orc_set_threads(int n);
 int orc_get_threads(void);
@@ -44,7 +51,10 @@ void orc_dct_matrix(double* c64);                 /* C[a*8+u], orthonormal DCT-I
 void orc_hadamard(int n, double* h);              /* Sylvester H_n / sqrt(n), n*n */
 void orc_kaiser(double beta, double* k8);         /* 8-tap Kaiser window */
 void orc_opponent(double* t9);                    /* T[k*3+c] */
-void orc_transform3d(const double* g, int n, double* s, int inverse); /* [n][8][8] */
+void orc_transform3d(const double* g, int n, double* s, int inverse); /* [n][8][8], DCT */
+void orc_bior15_filters(double* lo10);            /* analysis lowpass, offsets -4..5 */
+void orc_bior15_matrix(double* fwd64, double* inv64); /* F[a*8+u], its inverse I[u*8+a] */
+void orc_transform3d_ex(const double* g, int n, double* s, int inverse, int transform);
 
 /* stage functions */
 void orc_prepare(const uint8_t* img, int h, int w, int c, double* planar, uint8_t* lum);
@@ -52,6 +62,8 @@ void orc_match_u8(const uint8_t* lum, int h, int w, int S, int nmax, double tau,
                   int32_t* idx, int32_t* cnt);
 void orc_match_f64(const double* lum, int h, int w, int S, int nmax, double tau,
                    int32_t* idx, int32_t* cnt);
+void orc_match_prefiltered(const uint8_t* lum, int h, int w, int S, int nmax, double tau,
+                           double thr2d, int transform, int32_t* idx, int32_t* cnt);
 void orc_filter(const double* noisy, const double* basic, int h, int w, int c,
                 double sigma, int step, const int32_t* idx, const int32_t* cnt, int nmax,
                 const orc_params* p, double* num, double* den, double* margin, int32_t* nkept);

@@ -37,10 +37,13 @@ def all_patches(plane):
     return sliding_window_view(plane, (PATCH, PATCH)).reshape(h - 7, w - 7, 64)
 
 
-def match(lum, S, nmax, tau):
-    lum = np.asarray(lum, np.float64)
-    h, w = lum.shape
-    P = all_patches(lum)
+def match(lum, S, nmax, tau, P=None, shape=None):
+    if P is None:
+        lum = np.asarray(lum, np.float64)
+        h, w = lum.shape
+        P = all_patches(lum)
+    else:
+        h, w = shape
     rows, cols = grid(h), grid(w)
     idx = np.full((len(rows) * len(cols), nmax), -1, np.int32)
     cnt = np.zeros(len(rows) * len(cols), np.int32)
@@ -66,21 +69,76 @@ def match(lum, S, nmax, tau):
     return idx, cnt
 
 
-def t3d(group):
+# bior1.5 through its synthesis bank (the oracle builds it from the analysis
+# side): box lowpass at offsets 0, 1 and the highpass g[j] = (-1)^j lo[1-j],
+# lo the 10-tap spline lowpass at offsets -4..5; three periodic levels.
+BIOR_LO = np.array([3, -3, -22, 22, 128, 128, 22, -22, -3, 3]) * np.sqrt(2.0) / 256.0
+
+
+def _synthesis_level(n):
+    """n x n operator taking [a (n/2), d (n/2)] to a periodic signal of length n."""
+    S = np.zeros((n, n))
+    for k in range(n // 2):
+        S[(2 * k) % n, k] += 1 / np.sqrt(2.0)
+        S[(2 * k + 1) % n, k] += 1 / np.sqrt(2.0)
+        for j in range(-4, 6):
+            S[(2 * k + j) % n, n // 2 + k] += (-1.0) ** j * BIOR_LO[(1 - j) + 4]
+    return S
+
+
+def bior15_pair():
+    """(F, I): forward matrix with unit-norm rows (coefficients [a3, d3, d2,
+    d1]) and its inverse, from the multilevel synthesis operator."""
+    S = np.zeros((8, 8))
+    for c in range(8):
+        e = np.zeros(8)
+        e[c] = 1.0
+        a2 = _synthesis_level(2) @ e[0:2]                          # a3, d3 -> a2
+        a1 = _synthesis_level(4) @ np.concatenate([a2, e[2:4]])    # a2, d2 -> a1
+        S[:, c] = _synthesis_level(8) @ np.concatenate([a1, e[4:8]])  # a1, d1 -> x
+    F = np.linalg.inv(S)
+    F /= np.linalg.norm(F, axis=1, keepdims=True)
+    return F, np.linalg.inv(F)
+
+
+def t2d(group, transform):
+    if transform == 0:
+        return scipy.fft.dctn(group, type=2, norm="ortho", axes=(-2, -1))
+    F, _ = bior15_pair()
+    return np.einsum("au,...uv,bv->...ab", F, group, F)
+
+
+def it2d(spec, transform):
+    if transform == 0:
+        return scipy.fft.idctn(spec, type=2, norm="ortho", axes=(-2, -1))
+    _, I = bior15_pair()
+    return np.einsum("ua,...ab,vb->...uv", I, spec, I)
+
+
+def t3d(group, transform=0):
     n = group.shape[0]
     H = scipy.linalg.hadamard(n) / np.sqrt(n)
-    s2 = scipy.fft.dctn(group, type=2, norm="ortho", axes=(1, 2))
-    return np.tensordot(H, s2, axes=(1, 0))
+    return np.tensordot(H, t2d(group, transform), axes=(1, 0))
 
 
-def it3d(spec):
+def it3d(spec, transform=0):
     n = spec.shape[0]
     H = scipy.linalg.hadamard(n) / np.sqrt(n)
     g2 = np.tensordot(H.T, spec, axes=(1, 0))
-    return scipy.fft.idctn(g2, type=2, norm="ortho", axes=(1, 2))
+    return it2d(g2, transform)
 
 
-def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0):
+def match_prefiltered(lum, S, nmax, tau, thr2d, transform):
+    """Grouping on 2-D spectra of the patches hard-thresholded at thr2d
+    (vectorised: all patch spectra at once, then brute-force windows)."""
+    lum = np.asarray(lum, np.float64)
+    h, w = lum.shape
+    P = t2d(sliding_window_view(lum, (PATCH, PATCH)), transform)
+    P = np.where(np.abs(P) > thr2d, P, 0.0).reshape(h - 7, w - 7, 64)
+    return match(None, S, nmax, tau, P=P, shape=(h, w))
+
+
+def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0, transform=0):
     c, h, w = noisy.shape
     kw = np.kaiser(PATCH, beta)
     K = np.outer(kw, kw)
@@ -91,7 +149,8 @@ def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0):
         ys, xs = idx[r, :n] // w, idx[r, :n] % w
         for k in range(c):
             G = np.stack([noisy[k, y:y + 8, x:x + 8] for y, x in zip(ys, xs)])
-            S = t3d(G)
+            xf = transform if step == 1 else 0  # step 2 always uses the DCT
+            S = t3d(G, xf)
             if step == 1:
                 keep = np.abs(S) > lam * sigma
                 S = np.where(keep, S, 0.0)
@@ -104,7 +163,7 @@ def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0):
                 S = W * S
                 # the Wiener weight 1/sum W^2, capped at 2^10
                 wt = 1.0 / max(float((W * W).sum()), 2.0 ** -10)
-            E = it3d(S)
+            E = it3d(S, xf)
             for m, (y, x) in enumerate(zip(ys, xs)):
                 num[k, y:y + 8, x:x + 8] += wt * K * E[m]
                 den[k, y:y + 8, x:x + 8] += wt * K
@@ -112,7 +171,7 @@ def filt(noisy, basic, sigma, step, idx, cnt, lam=2.7, beta=2.0):
 
 
 def denoise(img, sigma, S_ht=16, S_wie=16, n_ht=16, n_wie=32, tau_ht=2500.0, tau_wie=400.0,
-            lam=2.7, beta=2.0):
+            lam=2.7, beta=2.0, transform=0, lam2d=0.0):
     img = np.asarray(img)
     if img.ndim == 2:
         Z = img[None].astype(np.float64)
@@ -121,8 +180,12 @@ def denoise(img, sigma, S_ht=16, S_wie=16, n_ht=16, n_wie=32, tau_ht=2500.0, tau
         Z = np.einsum("kc,hwc->khw", OPP, img.astype(np.float64))
         s = img.astype(np.int64).sum(-1)
         L1 = np.floor((s + 1) / 3.0)
-    i1, c1 = match(L1, S_ht, n_ht, tau_ht)
-    num, den = filt(Z, None, sigma, 1, i1, c1, lam, beta)
+    if lam2d > 0:
+        sl = sigma if img.ndim == 2 else sigma / np.sqrt(3.0)  # noise of the matching luminance
+        i1, c1 = match_prefiltered(L1, S_ht, n_ht, tau_ht, lam2d * sl, transform)
+    else:
+        i1, c1 = match(L1, S_ht, n_ht, tau_ht)
+    num, den = filt(Z, None, sigma, 1, i1, c1, lam, beta, transform)
     B = num / den
     L2 = B[0] if img.ndim == 2 else B[0] / np.sqrt(3.0)
     i2, c2 = match(L2, S_wie, n_wie, tau_wie)
