@@ -88,7 +88,20 @@ typedef struct {
                                 (a testing aid; NULL = not written) */
   void* workspace;           /* device memory for bm3d_denoise, >= bm3d_workspace_size() */
   size_t workspace_bytes;
+  /* variants of the published method (0 / BM3D_T_DCT: the default path) */
+  float lambda_2d;           /* > 0: step-1 grouping on 2-D spectra of the patches hard-
+                                thresholded at lambda_2d times the matching luminance's noise
+                                level (sigma grey, sigma/sqrt3 colour): the prefiltered
+                                matching of the high-noise profile (2.0 there) */
+  int transform_ht;          /* step-1 2-D transform: BM3D_T_DCT or BM3D_T_BIOR15 */
 } bm3d_params;
+
+/* Step-1 2-D patch transforms.  Step 2 always uses the DCT. */
+typedef enum {
+  BM3D_T_DCT = 0,   /* orthonormal 8x8 DCT-II */
+  BM3D_T_BIOR15 = 1 /* biorthogonal spline wavelet bior1.5, full dyadic decomposition on the
+                       periodic extension, forward rows of unit norm, inverse its matrix inverse */
+} bm3d_transform;
 
 /* Aggregation accumulators.  num and wsum are signed 64-bit fixed point
  * (value = integer / 2^BM3D_NUM_FRAC_BITS, resp. 2^BM3D_WSUM_FRAC_BITS).
@@ -115,7 +128,8 @@ typedef enum {
   BM3D_BUF_IDX2 = 8,   /* int32 [R][n_wie] step-2 groups */
   BM3D_BUF_CNT2 = 9,   /* int32 [R] step-2 group sizes */
   BM3D_BUF_NKEPT = 10, /* int32 [c][R] step-1 kept counts (BM3D_FLAG_DEBUG_NKEPT only; else 0 bytes) */
-  BM3D_NUM_BUFFERS = 11
+  BM3D_BUF_COEF = 11,  /* float [h-7][w-7][64] thresholded step-1 spectra (lambda_2d > 0; else 0 bytes) */
+  BM3D_NUM_BUFFERS = 12
 } bm3d_buffer;
 
 /* Defaults for noise level sigma: S=32 both steps, n 16/32, lambda 2.7,
@@ -153,6 +167,13 @@ int bm3d_prepare(const uint8_t* img, int h, int w, int c, float* planar, uint8_t
  * SSD <= 64*tau in increasing (SSD, index) order, truncated to n = the
  * largest power of two <= min(1 + #passing, n_max), n_max = n_ht or n_wie.
  * idx: device int32 [R][n_max], unused slots -1; cnt: device int32 [R] = n.
+ * With p->lambda_2d > 0, step 1 is the prefiltered grouping of the
+ * high-noise profile: distances between the patches' 2-D spectra
+ * (p->transform_ht) with every coefficient of magnitude <= the threshold set
+ * to 0, in FP32.  This call has no noise level, so the threshold is
+ * p->lambda_2d itself, an absolute level (bm3d_denoise uses lambda_2d times
+ * the luminance's noise level).  The spectra go to p->workspace, at least
+ * (h-7)*(w-7)*256 bytes (BM3D_ERR_WORKSPACE otherwise).
  * Invalid sizes, params or step/src_is_f32 pairs: BM3D_ERR_ARG, nothing
  * enqueued. */
 int bm3d_block_match(const void* src, int src_is_f32, int h, int w, int step,

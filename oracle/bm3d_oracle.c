@@ -395,24 +395,30 @@ void orc_match_prefiltered(const uint8_t* lum, int h, int w, int S, int nmax, do
   double* co = (double*)malloc(sizeof(double) * (size_t)ph * pw * 64);
   double F[64], I[64];
   transform_pair(transform, F, I);
+  /* The 2-D basis values F[a][u] F[b][v], rounded to 40 fractional bits:
+   * the rational ones (1/8 for the 2-D mean of either transform, and 1/4,
+   * 1/2 for bior1.5's Haar products) become exact, so a coefficient of
+   * integer pixels that equals the threshold in exact arithmetic equals it
+   * here as well and is not kept (the rule is |c| > threshold); the others
+   * move by at most 2^-41. */
+  double* B = (double*)malloc(sizeof(double) * 64 * 64);
+  for (int a = 0; a < P; a++)
+    for (int b = 0; b < P; b++)
+      for (int u = 0; u < P; u++)
+        for (int v = 0; v < P; v++)
+          B[(a * P + b) * 64 + u * P + v] = ldexp(nearbyint(ldexp(F[a * P + u] * F[b * P + v], 40)), -40);
 #pragma omp parallel for schedule(static) num_threads(g_threads)
   for (int y = 0; y < ph; y++)
     for (int x = 0; x < pw; x++) {
-      double t1[64];
       double* c = co + ((size_t)y * pw + x) * 64;
-      for (int u = 0; u < P; u++)
-        for (int b = 0; b < P; b++) {
-          double acc = 0.0;
-          for (int v = 0; v < P; v++) acc += F[b * P + v] * lum[(size_t)(y + u) * w + x + v];
-          t1[u * P + b] = acc;
-        }
-      for (int a = 0; a < P; a++)
-        for (int b = 0; b < P; b++) {
-          double acc = 0.0;
-          for (int u = 0; u < P; u++) acc += F[a * P + u] * t1[u * P + b];
-          c[a * P + b] = fabs(acc) > thr2d ? acc : 0.0;
-        }
+      for (int k = 0; k < 64; k++) {
+        double acc = 0.0;
+        for (int u = 0; u < P; u++)
+          for (int v = 0; v < P; v++) acc += B[k * 64 + u * P + v] * lum[(size_t)(y + u) * w + x + v];
+        c[k] = fabs(acc) > thr2d ? acc : 0.0;
+      }
     }
+  free(B);
   MATCH_BODY({
     double e = co[((size_t)ry * pw + rx) * 64 + u * P + v] - co[((size_t)qy * pw + qx) * 64 + u * P + v];
     d += e * e;

@@ -20,6 +20,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 XF_FP32, XF_BF16, XF_FP16 = 0, 1, 2
+T_DCT, T_BIOR15 = 0, 1  # step-1 2-D transforms
 FLAG_DEBUG_SYNC = 1
 FLAG_SIGMA_PROFILE = 2
 FLAG_DEBUG_NKEPT = 4
@@ -27,9 +28,9 @@ STAGES = ("prep", "match1", "filter1", "agg1", "match2", "filter2", "agg2")
 # working buffers of a workspace / batched plan (bm3d_buffer), with their
 # element types; num and wsum are fixed point with NUM_FRAC_BITS / WSUM_FRAC_BITS
 # fractional bits
-BUFFERS = ("planar", "lum8", "lumf", "basic", "num", "wsum", "idx1", "cnt1", "idx2", "cnt2", "nkept")
+BUFFERS = ("planar", "lum8", "lumf", "basic", "num", "wsum", "idx1", "cnt1", "idx2", "cnt2", "nkept", "coef")
 BUFFER_DTYPES = ("float32", "uint8", "float32", "float32", "int64", "int64", "int32", "int32", "int32", "int32",
-                 "int32")
+                 "int32", "float32")
 NUM_FRAC_BITS, WSUM_FRAC_BITS = 28, 40
 
 
@@ -41,7 +42,8 @@ class Params(ctypes.Structure):
                 ("xform", ctypes.c_int), ("tile_refs", ctypes.c_int),
                 ("persistent_wgs", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("debug_nkept", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("lambda_2d", ctypes.c_float), ("transform_ht", ctypes.c_int)]
 
     def copy(self) -> "Params":
         q = Params()

@@ -49,6 +49,8 @@ int check_params(const bm3d_params* p) {
   // range (it underflows near beta = 90), and the denominators with it
   if (p->kaiser_beta > kMaxKaiserBeta) return BM3D_ERR_UNSUPPORTED;
   if (p->xform < BM3D_XF_FP32 || p->xform > BM3D_XF_FP16) return BM3D_ERR_ARG;
+  if (!(p->lambda_2d >= 0.f) || !isfinite(p->lambda_2d)) return BM3D_ERR_ARG;
+  if (p->transform_ht != BM3D_T_DCT && p->transform_ht != BM3D_T_BIOR15) return BM3D_ERR_ARG;
   if (p->tile_refs < 0 || p->tile_refs > 16) return BM3D_ERR_ARG;
   if (p->persistent_wgs < 0 || p->persistent_wgs > 64) return BM3D_ERR_ARG;
   if (p->tile_refs > 0 && !tile_fits(p, p->tile_refs)) return BM3D_ERR_UNSUPPORTED;
@@ -74,8 +76,80 @@ double bessel_i0(double x) {
   return sum;
 }
 
+// 8-point orthonormal DCT-II, F[a][u]; its inverse is the transpose.
+void dct8(double* F, double* I) {
+  for (int a = 0; a < 8; a++)
+    for (int u = 0; u < 8; u++) {
+      const double v = (a == 0 ? sqrt(0.125) : 0.5) * cos(M_PI * (2 * u + 1) * a / 16.0);
+      F[a * 8 + u] = v;
+      I[u * 8 + a] = v;
+    }
+}
+
+// 8-point bior1.5 with full dyadic decomposition: the spline analysis
+// lowpass (10 taps symmetric about 1/2, sqrt2/256 [3 -3 -22 22 128 128 22 -22
+// -3 3] at offsets -4..5) and the Haar analysis highpass, three levels on the
+// periodic extension, coefficients coarse to fine [a3 d3 d2 d2 d1 d1 d1 d1];
+// forward rows scaled to unit norm (coefficients of white noise keep its
+// level), inverse by Gauss-Jordan elimination.
+void bior15_8(double* F, double* I) {
+  static const int tap[10] = {3, -3, -22, 22, 128, 128, 22, -22, -3, 3};
+  const double r2 = sqrt(2.0);
+  for (int u = 0; u < 8; u++) {
+    double sig[8] = {0}, out[8];
+    sig[u] = 1.0;
+    int len = 8, pos = 8;
+    while (len > 1) {  // one level: approximation in sig[0..len/2), details to out
+      double a[4], dd[4];
+      for (int k = 0; k < len / 2; k++) {
+        double acc = 0.0;
+        for (int j = -4; j <= 5; j++) acc += tap[j + 4] * r2 / 256.0 * sig[((2 * k + j) % len + len) % len];
+        a[k] = acc;
+        dd[k] = (sig[2 * k] - sig[2 * k + 1]) / r2;
+      }
+      pos -= len / 2;
+      for (int k = 0; k < len / 2; k++) {
+        out[pos + k] = dd[k];
+        sig[k] = a[k];
+      }
+      len /= 2;
+    }
+    out[0] = sig[0];
+    for (int a = 0; a < 8; a++) F[a * 8 + u] = out[a];
+  }
+  for (int a = 0; a < 8; a++) {
+    double nrm = 0.0;
+    for (int u = 0; u < 8; u++) nrm += F[a * 8 + u] * F[a * 8 + u];
+    nrm = sqrt(nrm);
+    for (int u = 0; u < 8; u++) F[a * 8 + u] /= nrm;
+  }
+  double m[8][16];  // [F | Id] -> [Id | F^-1]
+  for (int i = 0; i < 8; i++)
+    for (int j = 0; j < 16; j++) m[i][j] = j < 8 ? F[i * 8 + j] : (j == i + 8 ? 1.0 : 0.0);
+  for (int c = 0; c < 8; c++) {
+    int pv = c;
+    for (int r = c + 1; r < 8; r++)
+      if (fabs(m[r][c]) > fabs(m[pv][c])) pv = r;
+    for (int j = 0; j < 16; j++) std::swap(m[c][j], m[pv][j]);
+    const double d = m[c][c];
+    for (int j = 0; j < 16; j++) m[c][j] /= d;
+    for (int r = 0; r < 8; r++)
+      if (r != c) {
+        const double f = m[r][c];
+        for (int j = 0; j < 16; j++) m[r][j] -= f * m[c][j];
+      }
+  }
+  for (int u = 0; u < 8; u++)
+    for (int a = 0; a < 8; a++) I[u * 8 + a] = m[u][8 + a];
+}
+
 KParams make_kparams(const bm3d_params* p) {
   KParams k;
+  memset(&k, 0, sizeof k);
+  k.prefilter = p->lambda_2d > 0.f ? 1 : 0;
+  if (p->transform_ht == BM3D_T_BIOR15) bior15_8(k.f1, k.i1);
+  else dct8(k.f1, k.i1);
+  dct8(k.f2, k.i2);
   k.S1 = p->search_ht;
   k.S2 = p->search_wie;
   k.n1 = p->n_ht;
@@ -108,7 +182,11 @@ ImgDesc base_desc(int h, int w, int c, float sigma, const bm3d_params* p) {
     double t1 = 64.0 * (double)tau1;
     double cap = (double)((1u << 22) - 1);
     d.thr1 = (uint32_t)(t1 >= cap ? cap : floor(t1));
+    d.thr1f = 64.0f * tau1;
     d.thr2 = 64.0f * tau2;
+    // the matching luminance carries noise sigma (grey) or sigma/sqrt3 (the
+    // mean of three channels)
+    d.thr2d = p->lambda_2d * (c == 1 ? sigma : sigma * 0.57735026918962576f);
   }
   return d;
 }
@@ -116,6 +194,10 @@ ImgDesc base_desc(int h, int w, int c, float sigma, const bm3d_params* p) {
 bool want_sync(const bm3d_params* p) { return p && (p->flags & BM3D_FLAG_DEBUG_SYNC); }
 
 int run(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s, bool sync) {
+  if (stage == STAGE_MATCH1 && kp.prefilter) {  // thresholded spectra, then grouping on them
+    if (launch_single(STAGE_PREFILT, xform, d, kp, s, sync)) return BM3D_ERR_HIP;
+    stage = STAGE_MATCH1P;
+  }
   return launch_single(stage, xform, d, kp, s, sync) == 0 ? BM3D_OK : BM3D_ERR_HIP;
 }
 
@@ -139,6 +221,7 @@ Layout layout(int h, int w, int c, const bm3d_params* p) {
   L.bytes[BM3D_BUF_IDX2] = R * p->n_wie * 4;
   L.bytes[BM3D_BUF_CNT2] = R * 4;
   L.bytes[BM3D_BUF_NKEPT] = (p->flags & BM3D_FLAG_DEBUG_NKEPT) ? c * R * 4 : 0;
+  L.bytes[BM3D_BUF_COEF] = p->lambda_2d > 0.f ? (size_t)(h - kP + 1) * (w - kP + 1) * 64 * 4 : 0;
   size_t o = 0;
   for (int b = 0; b < BM3D_NUM_BUFFERS; b++) {
     L.off[b] = o;
@@ -160,6 +243,7 @@ void bind_workspace(ImgDesc& d, char* base, const Layout& L) {
   d.idx2 = (int32_t*)(base + L.off[BM3D_BUF_IDX2]);
   d.cnt2 = (int32_t*)(base + L.off[BM3D_BUF_CNT2]);
   d.nkept = L.bytes[BM3D_BUF_NKEPT] ? (int32_t*)(base + L.off[BM3D_BUF_NKEPT]) : nullptr;
+  d.coef = L.bytes[BM3D_BUF_COEF] ? (float*)(base + L.off[BM3D_BUF_COEF]) : nullptr;
 }
 
 }  // namespace
@@ -235,12 +319,18 @@ extern "C" int bm3d_block_match(const void* src, int src_is_f32, int h, int w, i
   if ((e = check_params(p))) return e;
   if (!src || !idx || !cnt) return BM3D_ERR_ARG;
   if (!((step == 1 && !src_is_f32) || (step == 2 && src_is_f32))) return BM3D_ERR_ARG;
-  ImgDesc d = base_desc(h, w, 1, 0.f, p);
+  // no noise level here: a prefilter threshold is lambda_2d itself (level 1)
+  ImgDesc d = base_desc(h, w, 1, 1.f, p);
   KParams kp = make_kparams(p);
   if (step == 1) {
     d.lum8 = (uint8_t*)src;
     d.idx1 = idx;
     d.cnt1 = cnt;
+    if (kp.prefilter) {  // the thresholded spectra go to params->workspace
+      const size_t need = (size_t)(h - kP + 1) * (w - kP + 1) * 64 * 4;
+      if (!p->workspace || p->workspace_bytes < need) return BM3D_ERR_WORKSPACE;
+      d.coef = (float*)p->workspace;
+    }
   } else {
     d.lumf = (float*)src;
     d.idx2 = idx;
@@ -379,6 +469,11 @@ void fill_prefix(const ImgDesc* d, int n, const KParams& kp, std::vector<int>* p
 }
 
 int batch_stage(bm3d_batch* b, int stage, int i0, int i1, hipStream_t s) {
+  if (stage == STAGE_MATCH1 && b->kp.prefilter) {
+    const int e = batch_stage(b, STAGE_PREFILT, i0, i1, s);
+    if (e != BM3D_OK) return e;
+    stage = STAGE_MATCH1P;
+  }
   const int L = list_of_stage(stage);
   BatchRef br{b->dd, b->dprefix[L], b->n, b->hprefix[L][i0], b->hprefix[L][i1]};
   if (stage == STAGE_FILTER1 || stage == STAGE_FILTER2) br.ctr = b->ctr;
@@ -554,7 +649,9 @@ struct bm3d_server {
 
 namespace {
 // per stage group: descriptors, prefix of its own list, prefix of the fill list
-size_t group_bytes(int m) { return align_up(sizeof(ImgDesc) * m) + 2 * align_up(sizeof(int) * (m + 1)); }
+// per stage group: descriptors, prefix counts of its own list, of the fill
+// list and of the prefilter list
+size_t group_bytes(int m) { return align_up(sizeof(ImgDesc) * m) + 3 * align_up(sizeof(int) * (m + 1)); }
 }  // namespace
 
 extern "C" int bm3d_server_create(int max_requests, const bm3d_params* p, bm3d_server** out) {
@@ -619,10 +716,12 @@ extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
     const int m = cnt[stg];
     int* pre = (int*)(hb + o + align_up(sizeof(ImgDesc) * m));
     int* pfill = (int*)((char*)pre + align_up(sizeof(int) * (m + 1)));
-    pre[0] = pfill[0] = 0;
+    int* ppre = (int*)((char*)pfill + align_up(sizeof(int) * (m + 1)));
+    pre[0] = pfill[0] = ppre[0] = 0;
     for (int i = 0; i < m; i++) {
       pre[i + 1] = pre[i] + items_of(list_of_stage(stg), dsc[i], s->kp.tile, elem_chunk());
       pfill[i + 1] = pfill[i] + items_of(LIST_PLANE, dsc[i], s->kp.tile, elem_chunk());
+      ppre[i + 1] = ppre[i] + items_of(LIST_PREFILT, dsc[i], s->kp.tile, elem_chunk());
     }
     o += group_bytes(m);
   }
@@ -639,7 +738,16 @@ extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
     const int* hfill = (const int*)((const char*)hpre + align_up(sizeof(int) * (m + 1)));
     BatchRef br{dd, pre, m, 0, hpre[m]};
     if (stg == STAGE_FILTER1 || stg == STAGE_FILTER2) br.ctr = (int*)(s->dev[k] + s->table_bytes);
-    if (launch_batch(stg, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p), s->cus)) return BM3D_ERR_HIP;
+    int launch_stage = stg;
+    if (stg == STAGE_MATCH1 && s->kp.prefilter) {  // thresholded spectra first, on their own list
+      const int* ppre = (const int*)((const char*)pfill + align_up(sizeof(int) * (m + 1)));
+      const int* hppre = (const int*)((const char*)hfill + align_up(sizeof(int) * (m + 1)));
+      BatchRef bp{dd, ppre, m, 0, hppre[m]};
+      if (launch_batch(STAGE_PREFILT, s->p.xform, bp, s->kp, blocks, st, want_sync(&s->p), s->cus))
+        return BM3D_ERR_HIP;
+      launch_stage = STAGE_MATCH1P;
+    }
+    if (launch_batch(launch_stage, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p), s->cus)) return BM3D_ERR_HIP;
     if (stg == STAGE_PREP || stg == STAGE_AGG1) {
       BatchRef bf{dd, pfill, m, 0, hfill[m]};
       if (launch_batch(STAGE_FILL, s->p.xform, bf, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;

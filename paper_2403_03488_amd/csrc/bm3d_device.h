@@ -58,6 +58,9 @@ struct ImgDesc {
   float lam_sigma;     // lambda * sigma
   uint32_t thr1;       // step-1 integer SSD bound floor(64 tau_ht), <= 2^22-1
   float thr2;          // step-2 SSD bound 64 tau_wie
+  float* coef;         // prefiltered matching: [(h-7)(w-7)][64] thresholded 2-D spectra
+  float thr2d;         // their threshold: lambda_2d times the luminance's noise level
+  float thr1f;         // prefiltered matching: distance bound 64 tau_ht
 };
 
 // Aggregation tile (pixels): one 256-thread workgroup item.
@@ -71,7 +74,12 @@ struct KParams {
   int S1, S2;       // search sides
   int n1, n2;       // max group sizes
   int tile;         // filter tile side in references
+  int prefilter;    // step-1 matching on thresholded 2-D spectra (lambda_2d > 0)
   float kaiser[8];  // 1-D Kaiser window
+  // 8-point transforms of the 2-D patch transforms, in double so that the
+  // 2-D products are rounded once: forward F[a][u] and inverse I[u][a] of
+  // step 1 (DCT or bior1.5) and of step 2 (DCT)
+  double f1[64], i1[64], f2[64], i2[64];
 };
 
 // ------------------------------------------------- global-memory access ---

@@ -586,6 +586,173 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
     }
   }
 }
+// ================================================== prefiltered step-1 ==
+// The high-noise profile of the published method groups on denoised
+// patches: each 8x8 patch of the matching luminance is taken to its 2-D
+// spectrum (the step-1 transform) and coefficients with |c| <= thr2d are
+// set to zero; distances are squared Euclidean distances of these spectra.
+// They are FP32, so groups are compared with the exact ones as valid
+// ordered top-n sets, not bit for bit.
+//
+// prefilt: the thresholded spectra of every patch position, as FP32 matrix
+// products of 16 positions x 64 pixels by the 64 x 64 transform table per
+// wave (the table's rational entries are exact, so are the spectra's).
+constexpr int kPrefiltPerWave = 16, kPrefiltPerItem = 4 * kPrefiltPerWave;
+static_assert(kPrefiltPerItem == kPrefiltItemPositions, "work list and kernel agree on the item size");
+__host__ __device__ inline int prefilt_items(int h, int w) {
+  return ((h - kP + 1) * (w - kP + 1) + kPrefiltPerItem - 1) / kPrefiltPerItem;
+}
+__host__ __device__ inline size_t prefilt_lds_bytes() { return (size_t)16 * 64 * sizeof(f32x4) * 2; }
+
+__device__ void prefilt_item(const ImgDesc& d, const KParams& kp, int item, const f32x4* tabB) {
+  const int l = lane_id(), q = l >> 4, col = l & 15, wave = threadIdx.x >> 6;
+  const int pw = d.w - kP + 1, npos = (d.h - kP + 1) * pw;
+  const int p0 = item * kPrefiltPerItem + wave * kPrefiltPerWave;
+  if (p0 >= npos) return;
+  // A operand: row = position p0 + col, contraction = pixel 16 kt + 4 q + v,
+  // i.e. patch row 2 kt + q/2, columns 4 (q&1) .. +3
+  const int pp = min(p0 + col, npos - 1);  // in-range stand-in past the end
+  const int py = pp / pw, px = pp - py * pw;
+  f32x4 a[4];
+#pragma unroll
+  for (int kt = 0; kt < 4; kt++) {
+    const uint8_t* src = d.lum8 + (size_t)(py + 2 * kt + (q >> 1)) * d.w + px + 4 * (q & 1);
+#pragma unroll
+    for (int v = 0; v < 4; v++) a[kt][v] = (float)ldg(src + v);
+  }
+  f32x4 acc[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; nt++) {
+    acc[nt] = zero4();
+#pragma unroll
+    for (int k2 = 0; k2 < 2; k2++) {
+      const f32x4* tb = tabB + ((k2 * 4 + nt) * 64 + l) * 2;
+      acc[nt] = XF32::mma2(a[2 * k2], a[2 * k2 + 1], tb[0], tb[1], acc[nt]);
+    }
+  }
+  // accumulator: position p0 + 4 q + v, coefficient 16 nt + col
+  const float thr = d.thr2d;
+#pragma unroll
+  for (int v = 0; v < 4; v++) {
+    const int pos = p0 + 4 * q + v;
+    if (pos >= npos) continue;
+    float* o = d.coef + (size_t)pos * 64 + col;
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++) stg(o + 16 * nt, fabsf(acc[nt][v]) > thr ? acc[nt][v] : 0.f);
+  }
+}
+
+// match1p: as match2 (wave b takes the block's reference column b, lane l
+// window row l/2 and 16 adjacent window columns) on spectra: the union
+// window's spectra pass through LDS kM1pChunk coefficients at a time, each
+// lane accumulating its candidates' distances to the four references.
+constexpr int kM1pChunk = 8;
+__host__ __device__ inline size_t match1p_lds_bytes(int S) {
+  const size_t chunk = (size_t)(S + 9) * (S + 9) * kM1pChunk * 4;
+  const size_t sel = (size_t)(kThreads / 64) * S * S * 8;  // selection scratch, after the distances
+  return (chunk > sel ? chunk : sel) + 16 * 64 * 4;          // + the references' spectra
+}
+
+__device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
+  const int S = kp.S1, nmax = kp.n1;
+  const int h = d.h, w = d.w, pw = w - kP + 1;
+  const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6;
+  const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
+  const int SH = g.SH, SW = g.SW, SS = SH * SW;
+  const size_t chunk_bytes = (size_t)(S + 9) * (S + 9) * kM1pChunk * 4, sel_bytes = (size_t)4 * S * S * 8;
+  float* chunk = (float*)smem;
+  uint64_t* bufs = (uint64_t*)smem;
+  float* refc = (float*)(smem + (chunk_bytes > sel_bytes ? chunk_bytes : sel_bytes));
+  for (int i = tid; i < 16 * 64; i += blockDim.x) {
+    const int m = i >> 6, a = m >> 2, b = m & 3;
+    float v = 0.f;
+    if (a < g.nri && b < g.nci) v = ldg(d.coef + ((size_t)ref_pos(g.ri0 + a, h) * pw + ref_pos(g.ci0 + b, w)) * 64 + (i & 63));
+    refc[i] = v;
+  }
+  const int b = wave;
+  const bool col_ok = b < g.nci;
+  const int wyy = l >> 1, wxx0 = (l & 1) * 16;
+  const bool lane_ok = col_ok && wyy < SH && wxx0 < SW;
+  const int rx = ref_pos(g.ci0 + (col_ok ? b : 0), w);
+  int wx, t0;
+  window_1d(rx, w, S, wx, t0);
+  const int na = g.nri;
+  int ry[4], wy[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    ry[a] = ref_pos(g.ri0 + min(a, na - 1), h);
+    window_1d(ry[a], h, S, wy[a], t0);
+  }
+  float acc[4][16];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int t = 0; t < 16; t++) acc[a][t] = 0.f;
+  const int nchunk = g.ny * g.nx * kM1pChunk;
+  for (int c0 = 0; c0 < 64; c0 += kM1pChunk) {
+    __syncthreads();  // the previous chunk has been read
+    for (int i = tid; i < nchunk; i += blockDim.x) {
+      const int pos = i / kM1pChunk, c = i - pos * kM1pChunk;
+      const int y = pos / g.nx, x = pos - y * g.nx;
+      chunk[i] = ldg(d.coef + ((size_t)(g.uy0 + y) * pw + g.ux0 + x) * 64 + c0 + c);
+    }
+    __syncthreads();
+    if (!lane_ok) continue;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      if (a >= na) break;
+      float cr[kM1pChunk];
+#pragma unroll
+      for (int c = 0; c < kM1pChunk; c++) cr[c] = refc[(a * 4 + b) * 64 + c0 + c];
+      const int cy = wy[a] - g.uy0 + wyy;
+#pragma unroll
+      for (int t = 0; t < 16; t++) {
+        const int cx = min(wx - g.ux0 + wxx0 + t, g.nx - 1);  // in-range stand-in past the window
+        const float* qv = chunk + ((size_t)cy * g.nx + cx) * kM1pChunk;
+        float s = acc[a][t];
+#pragma unroll
+        for (int c = 0; c < kM1pChunk; c++) {
+          const float e = cr[c] - qv[c];
+          s = __builtin_fmaf(e, e, s);
+        }
+        acc[a][t] = s;
+      }
+    }
+  }
+  __syncthreads();  // the chunk buffer becomes selection scratch
+  if (!col_ok) return;
+  const float thr = d.thr1f;
+#pragma unroll
+  for (int a = 0; a < 4; a++) {
+    if (a >= na) break;
+    uint32_t db[16], wi[16];
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+      const int wxx = wxx0 + t;
+      const bool isref = (wy[a] + wyy == ry[a]) && (wx + wxx == rx);
+      const bool ok = lane_ok && wxx < SW && !isref && acc[a][t] <= thr;
+      db[t] = ok ? __float_as_uint(acc[a][t]) : kNone32;
+      wi[t] = (uint32_t)(wyy * SW + wxx);
+    }
+    uint64_t sel;
+    const int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * SS, sel);
+    const size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
+    int32_t* o = d.idx1 + r * nmax;
+    if (l == 0) {
+      stg(o, ry[a] * w + rx);
+      stg(d.cnt1 + r, n);
+    }
+    if (l + 1 < nmax) {
+      int gi = -1;
+      if (l < n - 1) {
+        const int widx = (int)(sel & 1023u);
+        gi = (wy[a] + widx / SW) * w + wx + widx % SW;
+      }
+      stg(o + l + 1, gi);
+    }
+  }
+}
+
 // ========================================================= collaborative ==
 // Each wave filters the groups of its own T x T tile of references and
 // aggregates them into a wave-private LDS accumulator covering the tile's
@@ -618,7 +785,7 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
   static constexpr int kMaxWaves = 8;  // waves per workgroup at most
-  static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag) + 64 * 4; }
+  static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag); }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
   // region row pitch in 64-bit words: odd, so the rows of a member patch
   // spread over the LDS banks
@@ -661,18 +828,16 @@ __device__ inline typename XF::frag had_frag(int rt, int kt, int n) {
   return XF::cvt(a);
 }
 
-// Builds the two DCT fragment tables of a workgroup (caller synchronises).
+// Builds the two fragment tables of a workgroup's 2-D transform (caller
+// synchronises): forward B[pix][coef] = F[a][u] F[b][v] and inverse
+// A[pix][coef] = I[u][a] I[v][b] K(u) K(v), coef = (a, b), pix = (u, v), each
+// product formed in double and rounded once (the rational entries -- the
+// 2-D mean's 1/8, and bior1.5's 1/4 and 1/2 -- are then exact).
 template <class XF>
-__device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, float* Cm,
-                              const float* kaiser) {
+__device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, const double* F,
+                              const double* I, const float* kaiser, int ntab = 2) {
   const int tid = threadIdx.x;
-  if (tid < 64) {
-    int a = tid >> 3, u = tid & 7;
-    double s = a == 0 ? 0.35355339059327376 : 0.5;
-    Cm[tid] = (float)(s * cos(3.14159265358979323846 * (2 * u + 1) * a / 16.0));
-  }
-  __syncthreads();
-  for (int i = tid; i < 2 * 16 * 64; i += blockDim.x) {
+  for (int i = tid; i < ntab * 16 * 64; i += blockDim.x) {
     int tab = i >> 10, f = (i >> 6) & 15, ln = i & 63;
     int lq = ln >> 4, lc = ln & 15;
     f32x4 v4;
@@ -685,13 +850,10 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
         pix = 16 * (f >> 2) + lc;
         coef = 16 * (f & 3) + 4 * lq + v;
       }
-      // the 2-D mean's basis value is exactly 1/8 (fl(1/sqrt8)^2 is not): the
-      // mean coefficient of integer pixels is then exact, so it sits on the
-      // same side of a threshold that is a multiple of 1/32 as in exact
-      // arithmetic (lambda sigma = 40.5, 67.5, 135 at sigma 15, 25, 50)
-      v4[v] = coef == 0 ? 0.125f : Cm[(coef >> 3) * 8 + (pix >> 3)] * Cm[(coef & 7) * 8 + (pix & 7)];
+      const int a = coef >> 3, b = coef & 7, u = pix >> 3, vv = pix & 7;
       // the inverse table carries the Kaiser weight of its output pixel
-      if (tab == 1) v4[v] *= kaiser[pix >> 3] * kaiser[pix & 7];
+      v4[v] = tab == 0 ? (float)(F[a * 8 + u] * F[b * 8 + vv])
+                       : (float)(I[u * 8 + a] * I[vv * 8 + b] * (double)kaiser[u] * (double)kaiser[vv]);
     }
     // stored so that the two tiles of one 32-deep contraction step are
     // adjacent for each lane: B at ((kt/2)*4 + nt, lane, kt%2), A at
@@ -1016,8 +1178,7 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   typedef FilterCfg<XF> C;
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
-  float* Cm = (float*)(tabA + 16 * 64);
-  filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
+  filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1043,8 +1204,7 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   typedef FilterCfg<XF> C;
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
-  float* Cm = (float*)(tabA + 16 * 64);
-  filter_tables<XF>(tabB, tabA, Cm, kp.kaiser);
+  filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
   __syncthreads();
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   // the work index is wave-uniform, so the descriptor below is read once
@@ -1119,6 +1279,29 @@ __global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br, KPar
     else lum_chunk(d, j);
   }
 }
+__global__ void __launch_bounds__(kThreads) k_prefilt(ImgDesc d, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  f32x4* tabB = (f32x4*)smem;
+  filter_tables<XF32>(tabB, nullptr, kp.f1, kp.i1, kp.kaiser, 1);
+  __syncthreads();
+  prefilt_item(d, kp, blockIdx.x, tabB);
+}
+__global__ void __launch_bounds__(kThreads) k_match1p(ImgDesc d, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  match1p_block(d, kp, blockIdx.y, blockIdx.x, smem);
+}
+__global__ void __launch_bounds__(kThreads) kb_prefilt(BatchRef br, KParams kp) {
+  extern __shared__ __align__(16) char smem[];
+  f32x4* tabB = (f32x4*)smem;
+  filter_tables<XF32>(tabB, nullptr, kp.f1, kp.i1, kp.kaiser, 1);
+  __syncthreads();
+  for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
+    const int im = find_img(br.prefix, br.nimg, i);
+    const ImgDesc d = ldc(br.ds + im);
+    prefilt_item(d, kp, i - br.prefix[im], tabB);
+  }
+}
+
 template <int STEP>
 __global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
@@ -1128,6 +1311,7 @@ __global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
     const int j = i - br.prefix[im];
     const int nbx = (d.nc + 3) / 4;
     if (STEP == 1) match1_block(d, kp, j / nbx, j % nbx, smem);
+    else if (STEP == 3) match1p_block(d, kp, j / nbx, j % nbx, smem);  // prefiltered step 1
     else match2_block(d, kp, j / nbx, j % nbx, smem);
     __syncthreads();
   }
@@ -1171,6 +1355,18 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
     case STAGE_LUM:
       hipLaunchKernelGGL(k_lum, dim3(elem_blocks(d, false)), dim3(kThreads), 0, s, d);
       break;
+    case STAGE_PREFILT: {
+      size_t b = prefilt_lds_bytes();
+      lds_attr(k_prefilt, b);
+      hipLaunchKernelGGL(k_prefilt, dim3(prefilt_items(d.h, d.w)), dim3(kThreads), b, s, d, kp);
+      break;
+    }
+    case STAGE_MATCH1P: {
+      size_t b = match1p_lds_bytes(kp.S1);
+      lds_attr(k_match1p, b);
+      hipLaunchKernelGGL(k_match1p, dim3((d.nc + 3) / 4, (d.nr + 3) / 4), dim3(kThreads), b, s, d, kp);
+      break;
+    }
     case STAGE_MATCH1:
     case STAGE_MATCH2: {
       dim3 grid((d.nc + 3) / 4, (d.nr + 3) / 4);
@@ -1233,6 +1429,18 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
       hipLaunchKernelGGL(kb_match<1>, dim3(grid), dim3(kThreads), b, s, br, kp);
       break;
     }
+    case STAGE_PREFILT: {
+      size_t b = prefilt_lds_bytes();
+      lds_attr(kb_prefilt, b);
+      hipLaunchKernelGGL(kb_prefilt, dim3(grid), dim3(kThreads), b, s, br, kp);
+      break;
+    }
+    case STAGE_MATCH1P: {
+      size_t b = match1p_lds_bytes(kp.S1);
+      lds_attr(kb_match<3>, b);
+      hipLaunchKernelGGL(kb_match<3>, dim3(grid), dim3(kThreads), b, s, br, kp);
+      break;
+    }
     case STAGE_MATCH2: {
       size_t b = match2_lds_bytes(kp.S2, kThreads / 64);
       lds_attr(kb_match<2>, b);
@@ -1271,6 +1479,8 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
 size_t stage_lds_bytes(int stage, int xform, const KParams& kp) {
   switch (stage) {
     case STAGE_MATCH1: return match1_lds_bytes(kp.S1);
+    case STAGE_PREFILT: return prefilt_lds_bytes();
+    case STAGE_MATCH1P: return match1p_lds_bytes(kp.S1);
     case STAGE_MATCH2: return match2_lds_bytes(kp.S2, kThreads / 64);
     case STAGE_FILTER1: return filter_lds_bytes(xform, kp.S1, kp.tile);
     case STAGE_FILTER2: return filter_lds_bytes(xform, kp.S2, kp.tile);

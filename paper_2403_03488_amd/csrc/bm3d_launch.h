@@ -15,22 +15,30 @@ enum Stage {
   STAGE_MATCH2 = 4,
   STAGE_FILTER2 = 5,
   STAGE_AGG2 = 6,
-  STAGE_FILL = 7,  // zero num/den
-  STAGE_LUM = 8    // step-2 luminance from a planar basic estimate
+  STAGE_FILL = 7,     // zero num/den
+  STAGE_LUM = 8,      // step-2 luminance from a planar basic estimate
+  STAGE_PREFILT = 9,  // prefiltered step-1 matching: thresholded 2-D spectra
+  STAGE_MATCH1P = 10  // prefiltered step-1 matching: grouping on them
 };
 
 // Batched launches decode their work arithmetically: for every image the
 // number of items of a stage is a function of its size (elementwise chunks,
 // 4x4-reference matching blocks, or channel x filter tiles), so a launch only
 // needs the image descriptors and the per-image prefix counts.
-enum ListKind { LIST_PIX = 0, LIST_PLANE = 1, LIST_MATCH = 2, LIST_FILTER = 3, LIST_AGG = 4, LIST_KINDS = 5 };
+enum ListKind {
+  LIST_PIX = 0, LIST_PLANE = 1, LIST_MATCH = 2, LIST_FILTER = 3, LIST_AGG = 4, LIST_PREFILT = 5, LIST_KINDS = 6
+};
+
+// patch positions per prefilter work item
+constexpr int kPrefiltItemPositions = 64;
 
 __host__ __device__ inline int list_of_stage(int stage) {
   switch (stage) {
     case STAGE_PREP: case STAGE_LUM: return LIST_PIX;
     case STAGE_AGG1: case STAGE_AGG2: return LIST_AGG;
     case STAGE_FILL: return LIST_PLANE;
-    case STAGE_MATCH1: case STAGE_MATCH2: return LIST_MATCH;
+    case STAGE_MATCH1: case STAGE_MATCH2: case STAGE_MATCH1P: return LIST_MATCH;
+    case STAGE_PREFILT: return LIST_PREFILT;
     default: return LIST_FILTER;
   }
 }
@@ -42,6 +50,8 @@ __host__ __device__ inline int items_of(int list, const ImgDesc& d, int tile, in
     case LIST_PLANE: return (int)((hw * d.c + chunk - 1) / chunk);
     case LIST_MATCH: return ((d.nr + 3) / 4) * ((d.nc + 3) / 4);
     case LIST_AGG: return agg_items(d.h, d.w);
+    case LIST_PREFILT:
+      return (int)(((long long)(d.h - kP + 1) * (d.w - kP + 1) + kPrefiltItemPositions - 1) / kPrefiltItemPositions);
     default: return d.c * ((d.nr + tile - 1) / tile) * ((d.nc + tile - 1) / tile);
   }
 }

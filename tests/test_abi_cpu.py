@@ -42,8 +42,8 @@ def test_every_declared_symbol_is_exported(B):
 
 
 def test_struct_layout_matches_header(B):
-    # bm3d_params: 4 ints, 4 floats, 4 ints/unsigned, 2 pointers, size_t
-    assert ctypes.sizeof(B.Params) == 4 * 4 + 4 * 4 + 4 * 4 + 8 + 8 + 8
+    # bm3d_params: 4 ints, 4 floats, 4 ints/unsigned, 2 pointers, size_t, float, int
+    assert ctypes.sizeof(B.Params) == 4 * 4 + 4 * 4 + 4 * 4 + 8 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(B.ImageDesc) == 8 + 8 + 3 * 4 + 4
 
 
@@ -225,7 +225,8 @@ def test_host_validation_rejects_before_enqueue(B):
     # invalid parameters
     for field, val in (("n_wie", 24), ("n_ht", 0), ("search_ht", 33), ("search_wie", 0),
                        ("lambda_ht", -1.0), ("tau_wie", float("nan")), ("xform", 7),
-                       ("kaiser_beta", float("inf")), ("tile_refs", 17)):
+                       ("kaiser_beta", float("inf")), ("tile_refs", 17), ("lambda_2d", -1.0),
+                       ("lambda_2d", float("nan")), ("transform_ht", 2)):
         q = p.copy()
         setattr(q, field, val)
         assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(q), fake, None) == -1, field
@@ -241,6 +242,9 @@ def test_host_validation_rejects_before_enqueue(B):
     # stage entry points
     assert L.bm3d_block_match(fake, 1, 64, 64, 1, ref(p), fake, fake, None) == -1  # step 1 needs uint8
     assert L.bm3d_block_match(fake, 0, 64, 64, 3, ref(p), fake, fake, None) == -1
+    pre = p.copy()
+    pre.lambda_2d = 50.0  # prefiltered step-1 grouping needs workspace for the spectra
+    assert L.bm3d_block_match(fake, 0, 64, 64, 1, ref(pre), fake, fake, None) == -3
     assert L.bm3d_collab_filter(fake, fake, 64, 64, 1, 25.0, 1, fake, fake, ref(p), fake, fake,
                                 None) == -1  # step 1 takes no basic estimate
     assert L.bm3d_collab_filter(fake, None, 64, 64, 1, 25.0, 2, fake, fake, ref(p), fake, fake,
@@ -269,7 +273,7 @@ def test_workspace_buffers(B):
     R = B.num_refs(h, w)
     want = {"planar": 4 * c * h * w, "lum8": h * w, "lumf": 4 * h * w, "basic": 4 * c * h * w,
             "num": 8 * c * h * w, "wsum": 8 * c * h * w, "idx1": 4 * R * p.n_ht, "cnt1": 4 * R,
-            "idx2": 4 * R * p.n_wie, "cnt2": 4 * R, "nkept": 0}
+            "idx2": 4 * R * p.n_wie, "cnt2": 4 * R, "nkept": 0, "coef": 0}
     end = 0
     for name in B.BUFFERS:
         off, nb = B.workspace_buffer(h, w, c, p, name)
@@ -280,11 +284,14 @@ def test_workspace_buffers(B):
     off, nb = B.workspace_buffer(h, w, c, q, "nkept")
     assert nb == 4 * c * R and off + nb <= B.workspace_size(h, w, c, q)
     assert B.workspace_size(h, w, c, q) > B.workspace_size(h, w, c, p)
+    v = B.params_default(50.0, lambda_2d=2.0, transform_ht=B.T_BIOR15)
+    off, nb = B.workspace_buffer(h, w, c, v, "coef")
+    assert nb == 4 * 64 * (h - 7) * (w - 7) and off + nb <= B.workspace_size(h, w, c, v)
     with pytest.raises(B.BM3DError):
         B.workspace_buffer(4, w, c, p, "idx1")
     L = B._lib
     o, n = ctypes.c_size_t(), ctypes.c_size_t()
-    assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), 11, ctypes.byref(o), ctypes.byref(n)) == -1
+    assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), 12, ctypes.byref(o), ctypes.byref(n)) == -1
     assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), -1, ctypes.byref(o), ctypes.byref(n)) == -1
     assert L.bm3d_workspace_buffer(h, w, c, ctypes.byref(p), 0, None, ctypes.byref(n)) == -1
 

@@ -155,6 +155,26 @@ def test_match_prefiltered_bruteforce(transform, kind):
         assert np.mean(np.all(oi == bi, axis=1)) > 0.8
 
 
+@pytest.mark.parametrize("transform", [oracle.T_DCT, oracle.T_BIOR15])
+def test_prefilter_threshold_is_strict_at_exact_ties(transform):
+    # An 8x8 block of 100 at the corner of an image of 101.  The corner patch
+    # is flat: its only nonzero coefficient is the 2-D mean term, exactly
+    # 8 * 100 = 800 for both transforms (their first basis row is constant
+    # 1/sqrt(8)).  Its neighbours hold some 101s, so their mean terms lie in
+    # (800, 808].  At threshold 800 the corner's spectrum vanishes (800 is not
+    # > 800) and every other patch is at least 800^2 away: with 64 tau = 6400
+    # the corner reference groups alone.  Just below the tie its mean term is
+    # kept and the neighbours come within 8^2 + (small AC) of it.
+    lum = np.full((24, 24), 101, np.uint8)
+    lum[:8, :8] = 100
+    idx, cnt = oracle.match_prefiltered(lum, 16, 16, 100.0, 800.0, transform)
+    assert idx[0, 0] == 0
+    assert cnt[0] == 1
+    idx2, cnt2 = oracle.match_prefiltered(lum, 16, 16, 100.0, 800.0 - 1e-6, transform)
+    assert idx2[0, 0] == 0
+    assert cnt2[0] == 16
+
+
 def test_prefilter_without_threshold_is_plain_matching():
     # the orthonormal DCT keeps distances: with nothing thresholded the
     # spectral distance is the pixel SSD, so the groups hold the same
