@@ -128,7 +128,8 @@ typedef enum {
   BM3D_BUF_IDX2 = 8,   /* int32 [R][n_wie] step-2 groups */
   BM3D_BUF_CNT2 = 9,   /* int32 [R] step-2 group sizes */
   BM3D_BUF_NKEPT = 10, /* int32 [c][R] step-1 kept counts (BM3D_FLAG_DEBUG_NKEPT only; else 0 bytes) */
-  BM3D_BUF_COEF = 11,  /* float [h-7][w-7][64] thresholded step-1 spectra (lambda_2d > 0; else 0 bytes) */
+  BM3D_BUF_COEF = 11,  /* float [16][h-7][w-7][4] thresholded step-1 spectra: coefficient 4k+j of the
+                          patch at (y, x) sits at [k][y][x][j] (lambda_2d > 0; else 0 bytes) */
   BM3D_NUM_BUFFERS = 12
 } bm3d_buffer;
 

@@ -630,25 +630,33 @@ __device__ void prefilt_item(const ImgDesc& d, const KParams& kp, int item, cons
       acc[nt] = XF32::mma2(a[2 * k2], a[2 * k2 + 1], tb[0], tb[1], acc[nt]);
     }
   }
-  // accumulator: position p0 + 4 q + v, coefficient 16 nt + col
+  // accumulator: position p0 + 4 q + v, coefficient 16 nt + col, stored in
+  // the plane of its coefficient quad (16 nt + col) / 4
   const float thr = d.thr2d;
 #pragma unroll
   for (int v = 0; v < 4; v++) {
     const int pos = p0 + 4 * q + v;
     if (pos >= npos) continue;
-    float* o = d.coef + (size_t)pos * 64 + col;
 #pragma unroll
-    for (int nt = 0; nt < 4; nt++) stg(o + 16 * nt, fabsf(acc[nt][v]) > thr ? acc[nt][v] : 0.f);
+    for (int nt = 0; nt < 4; nt++) {
+      float* o = d.coef + ((size_t)(4 * nt + (col >> 2)) * npos + pos) * 4 + (col & 3);
+      stg(o, fabsf(acc[nt][v]) > thr ? acc[nt][v] : 0.f);
+    }
   }
 }
 
-// match1p: as match2 (wave b takes the block's reference column b, lane l
-// window row l/2 and 16 adjacent window columns) on spectra: the union
-// window's spectra pass through LDS kM1pChunk coefficients at a time, each
-// lane accumulating its candidates' distances to the four references.
-constexpr int kM1pChunk = 8;
+// match1p: as match2, wave b takes the block's reference column b, lane l
+// window row l/2 and the 16 window columns 2t + (l&1) (lane pairs read
+// adjacent records, so a row of lanes spreads over the LDS banks).  The
+// union window's spectra pass through LDS one coefficient quad at a time
+// (one 16-byte record per position, a plane per quad in HBM, so a window row
+// is one contiguous run); the next quad is loaded into registers while the
+// current one is used.  Each lane accumulates its candidates' distances to
+// the column's four references.
+constexpr int kM1pQuads = 16;
+constexpr int kM1pLoads = ((kMaxS + 9) * (kMaxS + 9) + kThreads - 1) / kThreads;
 __host__ __device__ inline size_t match1p_lds_bytes(int S) {
-  const size_t chunk = (size_t)(S + 9) * (S + 9) * kM1pChunk * 4;
+  const size_t chunk = (size_t)(S + 9) * (S + 9) * sizeof(f32x4);
   const size_t sel = (size_t)(kThreads / 64) * S * S * 8;  // selection scratch, after the distances
   return (chunk > sel ? chunk : sel) + 16 * 64 * 4;          // + the references' spectra
 }
@@ -656,23 +664,46 @@ __host__ __device__ inline size_t match1p_lds_bytes(int S) {
 __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
   const int S = kp.S1, nmax = kp.n1;
   const int h = d.h, w = d.w, pw = w - kP + 1;
+  const size_t npos = (size_t)(h - kP + 1) * pw;
   const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6;
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
   const int SH = g.SH, SW = g.SW, SS = SH * SW;
-  const size_t chunk_bytes = (size_t)(S + 9) * (S + 9) * kM1pChunk * 4, sel_bytes = (size_t)4 * S * S * 8;
-  float* chunk = (float*)smem;
+  const size_t chunk_bytes = (size_t)(S + 9) * (S + 9) * sizeof(f32x4), sel_bytes = (size_t)4 * S * S * 8;
+  f32x4* chunk = (f32x4*)smem;
   uint64_t* bufs = (uint64_t*)smem;
   float* refc = (float*)(smem + (chunk_bytes > sel_bytes ? chunk_bytes : sel_bytes));
+  const f32x4* coef4 = (const f32x4*)d.coef;
   for (int i = tid; i < 16 * 64; i += blockDim.x) {
-    const int m = i >> 6, a = m >> 2, b = m & 3;
+    const int m = i >> 6, a = m >> 2, b = m & 3, c = i & 63;
     float v = 0.f;
-    if (a < g.nri && b < g.nci) v = ldg(d.coef + ((size_t)ref_pos(g.ri0 + a, h) * pw + ref_pos(g.ci0 + b, w)) * 64 + (i & 63));
+    if (a < g.nri && b < g.nci) {
+      const size_t pos = (size_t)ref_pos(g.ri0 + a, h) * pw + ref_pos(g.ci0 + b, w);
+      v = ldg(d.coef + ((size_t)(c >> 2) * npos + pos) * 4 + (c & 3));
+    }
     refc[i] = v;
   }
+  // this thread's union-window records: LDS slot i = tid + 256 k, HBM
+  // position offset within a quad plane (slots past the union window load
+  // the window's first record and are not stored)
+  const int nun = g.ny * g.nx;
+  uint32_t src[kM1pLoads];  // byte offsets within a plane (a plane is below 4 GiB)
+#pragma unroll
+  for (int k = 0; k < kM1pLoads; k++) {
+    const int i = min(tid + k * kThreads, nun - 1);
+    const int y = i / g.nx, x = i - y * g.nx;
+    src[k] = (uint32_t)((g.uy0 + y) * pw + g.ux0 + x) * (uint32_t)sizeof(f32x4);
+  }
+  f32x4 pre[kM1pLoads];
+  auto load_quad = [&](int c4) {
+    const char* plane = (const char*)(coef4 + (size_t)c4 * npos);
+#pragma unroll
+    for (int k = 0; k < kM1pLoads; k++) pre[k] = ldg((const f32x4*)(plane + src[k]));
+  };
+  load_quad(0);
   const int b = wave;
   const bool col_ok = b < g.nci;
-  const int wyy = l >> 1, wxx0 = (l & 1) * 16;
-  const bool lane_ok = col_ok && wyy < SH && wxx0 < SW;
+  const int wyy = l >> 1, hx = l & 1;
+  const bool lane_ok = col_ok && wyy < SH;
   const int rx = ref_pos(g.ci0 + (col_ok ? b : 0), w);
   int wx, t0;
   window_1d(rx, w, S, wx, t0);
@@ -688,30 +719,31 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int t = 0; t < 16; t++) acc[a][t] = 0.f;
-  const int nchunk = g.ny * g.nx * kM1pChunk;
-  for (int c0 = 0; c0 < 64; c0 += kM1pChunk) {
-    __syncthreads();  // the previous chunk has been read
-    for (int i = tid; i < nchunk; i += blockDim.x) {
-      const int pos = i / kM1pChunk, c = i - pos * kM1pChunk;
-      const int y = pos / g.nx, x = pos - y * g.nx;
-      chunk[i] = ldg(d.coef + ((size_t)(g.uy0 + y) * pw + g.ux0 + x) * 64 + c0 + c);
-    }
+#pragma unroll 1
+  for (int c4 = 0; c4 < kM1pQuads; c4++) {
+    __syncthreads();  // the previous quad has been read
+#pragma unroll
+    for (int k = 0; k < kM1pLoads; k++)
+      if (tid + k * kThreads < nun) chunk[tid + k * kThreads] = pre[k];
     __syncthreads();
+    if (c4 + 1 < kM1pQuads) load_quad(c4 + 1);
     if (!lane_ok) continue;
+    // rows past the block repeat its last reference: the work is
+    // straight-line code (a branch here lets the compiler hoist every read)
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-      if (a >= na) break;
-      float cr[kM1pChunk];
-#pragma unroll
-      for (int c = 0; c < kM1pChunk; c++) cr[c] = refc[(a * 4 + b) * 64 + c0 + c];
-      const int cy = wy[a] - g.uy0 + wyy;
+      const f32x4 cr = *(const f32x4*)(refc + (min(a, na - 1) * 4 + b) * 64 + 4 * c4);
+      const f32x4* row = chunk + (size_t)(wy[a] - g.uy0 + wyy) * g.nx;
+      const int x0 = wx - g.ux0 + hx;
 #pragma unroll
       for (int t = 0; t < 16; t++) {
-        const int cx = min(wx - g.ux0 + wxx0 + t, g.nx - 1);  // in-range stand-in past the window
-        const float* qv = chunk + ((size_t)cy * g.nx + cx) * kM1pChunk;
+        // columns past the window (2t + hx >= SW) are never selected; they
+        // read on into the next row, and past the last row at most 31
+        // records into the references' spectra, which follow the chunk
+        const f32x4 qv = row[x0 + 2 * t];
         float s = acc[a][t];
 #pragma unroll
-        for (int c = 0; c < kM1pChunk; c++) {
+        for (int c = 0; c < 4; c++) {
           const float e = cr[c] - qv[c];
           s = __builtin_fmaf(e, e, s);
         }
@@ -728,7 +760,7 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
     uint32_t db[16], wi[16];
 #pragma unroll
     for (int t = 0; t < 16; t++) {
-      const int wxx = wxx0 + t;
+      const int wxx = 2 * t + hx;
       const bool isref = (wy[a] + wyy == ry[a]) && (wx + wxx == rx);
       const bool ok = lane_ok && wxx < SW && !isref && acc[a][t] <= thr;
       db[t] = ok ? __float_as_uint(acc[a][t]) : kNone32;
@@ -1286,7 +1318,7 @@ __global__ void __launch_bounds__(kThreads) k_prefilt(ImgDesc d, KParams kp) {
   __syncthreads();
   prefilt_item(d, kp, blockIdx.x, tabB);
 }
-__global__ void __launch_bounds__(kThreads) k_match1p(ImgDesc d, KParams kp) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_match1p(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   match1p_block(d, kp, blockIdx.y, blockIdx.x, smem);
 }
@@ -1302,8 +1334,12 @@ __global__ void __launch_bounds__(kThreads) kb_prefilt(BatchRef br, KParams kp) 
   }
 }
 
+// The prefiltered matcher's LDS allows four workgroups per CU; its register
+// budget is held to match, so the compiler does not trade occupancy for
+// hoisted LDS reads.
 template <int STEP>
-__global__ void __launch_bounds__(kThreads) kb_match(BatchRef br, KParams kp) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 4 : 1)))
+kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
     const int im = find_img(br.prefix, br.nimg, i);
