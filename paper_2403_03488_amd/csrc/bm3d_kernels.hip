@@ -18,6 +18,8 @@
 #include "bm3d_device.h"
 #include "bm3d_launch.h"
 
+#include <type_traits>
+
 #include <algorithm>
 
 namespace bm3d {
@@ -929,11 +931,10 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   int hn = 0;
   const int nrefs = g.nri * g.nci;
   // A reference's group size and member slots are loaded two references
-  // ahead; its member positions (and in step 1 the pixels of its members)
-  // are formed and loaded while the previous reference is inverted and
-  // aggregated (slots beyond the group hold -1 and are ignored below).  Step
-  // 2 loads its pixels when it uses them: holding them across the
-  // aggregation would spill registers there.
+  // ahead; its member positions and noisy member pixels are formed and
+  // loaded while the previous reference is inverted and aggregated (slots
+  // beyond the group hold -1 and are ignored below).  Step 2 issues the
+  // loads of its basic pixels before the noisy transform, which hides them.
   // The tile's references in row-major order, by global index: walked with
   // counters (an integer division on the scalar unit costs tens of
   // instructions).  One walk for the prefetch, one for the current reference.
@@ -957,7 +958,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   };
   int n_nx = 1, my_nx[2], mx_nx[2];
   bool mv_nx[2];
-  f32x4 an[2][4];  // step 1: noisy member pixels of the next reference
+  f32x4 an[2][4];  // noisy member pixels of the next reference
   auto stage = [&]() {
     // group size and everything derived from it are wave-uniform
     n_nx = __builtin_amdgcn_readfirstlane(min(max(cnt_nx, 1), nmax));
@@ -978,7 +979,7 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     }
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) {
-      if (STEP == 2 || (gt == 1 && n_nx <= 16)) break;
+      if (gt == 1 && n_nx <= 16) break;
 #pragma unroll
       for (int kt = 0; kt < 4; kt++) {
         const float* src = noisy + (size_t)(my_nx[gt] + 2 * kt + (q >> 1)) * w + mx_nx[gt] + 4 * (q & 1);
@@ -998,7 +999,6 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     // the group size and everything derived from it are wave-uniform (kept
     // in scalar registers: the transforms branch on them)
     const int n = __builtin_amdgcn_readfirstlane(n_nx);
-    const int NG = n > 16 ? 2 : 1;
     // the spectra are kept as H.D1 (the orthonormal WHT times sqrt n): the
     // threshold, the Wiener noise power and the inverse scale absorb sqrt n
     const float sqn = n == 1 ? 1.f : n == 2 ? 1.41421356237309505f : n == 4 ? 2.f
@@ -1017,28 +1017,35 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
         for (int b = 0; b < 2; b++) Hf[a][b] = had_frag<XF>(a, b, n);
     }
 
+    // The group body, compiled once per member-tile count (1: n <= 16, 2:
+    // n = 32), so that each is straight-line code the scheduler can interleave.
+    auto group = [&](auto ng_c) {
+    constexpr int NG = decltype(ng_c)::value;
     // ---- forward: 2-D DCT then WHT of the noisy (and in step 2 the basic) group
     f32x4 D2[2][4], D2b[2][4];
+    f32x4 ab[2][4];  // step 2: basic member pixels, in flight during the noisy transform
+    if (STEP == 2) {
+#pragma unroll
+      for (int gt = 0; gt < 2; gt++) {
+        if (gt >= NG) break;
+#pragma unroll
+        for (int kt = 0; kt < 4; kt++) {
+          const float* src = basic + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
+#pragma unroll
+          for (int v = 0; v < 4; v++) ab[gt][kt][v] = ldg(src + v);  // always a valid pixel
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the loads are issued before the noisy transform
+    }
 #pragma unroll
     for (int src_i = 0; src_i < (STEP == 2 ? 2 : 1); src_i++) {
-      const float* __restrict__ src0 = src_i == 0 ? noisy : basic;
-      __builtin_amdgcn_sched_barrier(0);  // one group's loads in flight at a time
       f32x4 D1[2][4];
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
         f32x4 a[4];
-        if (STEP == 1) {
 #pragma unroll
-          for (int kt = 0; kt < 4; kt++) a[kt] = an[gt][kt];
-        } else {
-#pragma unroll
-          for (int kt = 0; kt < 4; kt++) {
-            const float* src = src0 + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
-#pragma unroll
-            for (int v = 0; v < 4; v++) a[kt][v] = ldg(src + v);  // always a valid pixel
-          }
-        }
+        for (int kt = 0; kt < 4; kt++) a[kt] = src_i == 0 ? an[gt][kt] : ab[gt][kt];
         if (!all_present) {  // an absent member enters as a zero patch
 #pragma unroll
           for (int kt = 0; kt < 4; kt++)
@@ -1181,6 +1188,9 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       }
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
     }
+    };
+    if (n > 16) group(std::integral_constant<int, 2>());
+    else group(std::integral_constant<int, 1>());
   }
 
   // ---- flush: the region into num, four rows per iteration (all their LDS
