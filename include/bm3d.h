@@ -79,8 +79,8 @@ typedef struct {
   float tau_ht, tau_wie;     /* a candidate joins only if SSD <= 64*tau (INFINITY: no limit) */
   float kaiser_beta;         /* Kaiser window parameter of the aggregation, 0..50 (2.0) */
   int xform;                 /* bm3d_xform */
-  int tile_refs;             /* references per side of the tile one wavefront filters and
-                                aggregates (0 = auto); limited by the LDS budget */
+  int tile_refs;             /* references per side of the tile one workgroup filters and
+                                aggregates in LDS (0 = auto); limited by the LDS budget */
   int persistent_wgs;        /* batched pass: workgroups per CU (0 = one per tile) */
   unsigned flags;            /* BM3D_FLAG_* */
   int32_t* debug_nkept;      /* optional device int32 [c][R]: bm3d_collab_filter step 1

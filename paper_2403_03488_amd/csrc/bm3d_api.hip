@@ -27,10 +27,10 @@ bool is_pow2_upto32(int n) { return n >= 1 && n <= 32 && (n & (n - 1)) == 0; }
 constexpr size_t kLdsBudget = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr float kMaxKaiserBeta = 50.f;
 
-int auto_tile(int S) { return S >= 24 ? 4 : 6; }
+int auto_tile(int S) { return S >= 24 ? 10 : 12; }
 
-// The filter tile (references per side of one wave's tile) must leave every
-// kernel within the LDS budget.
+// The filter tile (references per side of one workgroup's tile) must leave
+// every kernel within the LDS budget.
 bool tile_fits(const bm3d_params* p, int T) {
   for (int S : {p->search_ht, p->search_wie})
     if (stage_lds_bytes(STAGE_FILTER1, p->xform, KParams{S, S, 1, 1, T, {0}}) > kLdsBudget) return false;
@@ -884,7 +884,7 @@ extern "C" int bm3d_autotune(bm3d_params* p, const char* cache_path) {
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const int tiles[] = {2, 3, 4, 5, 6};
+  const int tiles[] = {6, 8, 10, 12, 14, 16};
   const int grids[] = {0, 1, 2, 4};
   float best = 1e30f;
   int bt = auto_tile(std::max(p->search_ht, p->search_wie)), bg = 0;

@@ -803,40 +803,41 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 //   D4[pix][g]    = sum_coef CC^T[pix][coef] D3[coef][g]     inverse 2-D DCT
 // Each product's accumulator feeds the next one without data movement.
 //
-// Exact aggregation in LDS.  The wave's region accumulates signed 64-bit
-// fixed point (kNumFrac fractional bits) with LDS integer atomics: straight
-// from the inverse DCT's accumulator layout, lane (q, member m) adds its 16
-// pixels of member m at one base address plus immediate offsets, with no
-// transposition and no ordering between members (integer additions are
-// exact and commute).  The region is then added into num with one global
-// 64-bit atomic per touched pixel, with no conversion.  Filtered values are
+// Exact aggregation in LDS.  A workgroup takes a T x T tile of references;
+// its waves draw the tile's references from a counter in LDS and add every
+// filtered member into one region covering the tile's search windows, as
+// signed 64-bit fixed point (kNumFrac fractional bits) with LDS integer
+// atomics: straight from the inverse DCT's accumulator layout, lane
+// (q, member m) adds its 16 pixels of member m at one base address plus
+// immediate offsets, with no transposition and no ordering between members
+// or waves (integer additions are exact and commute).  When the tile is
+// done the workgroup adds the region into num with one global 64-bit atomic
+// per touched pixel, with no conversion, and clears it.  Filtered values are
 // accumulated relative to the channel centre (bm3d_aggregate adds it back
 // as centre * den), which keeps the sums small.  The denominator sum of
 // w K(u)K(v) over member placements equals the Kaiser window correlated with
 // the per-position sum of group weights, so the filter adds each member's
 // weight once, at its corner, into a global weight map (wsum); the
 // aggregation forms the denominator from it.
+// Four waves per workgroup and two workgroups per CU (the filters hold up
+// to 256 registers per lane): while one workgroup waits for its slowest wave
+// or flushes, the other keeps the SIMDs busy.
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
-  static constexpr int kMaxWaves = 8;  // waves per workgroup at most
+  static constexpr int kWaves = 4;   // waves per workgroup
+  static constexpr int kPerCU = 2;   // workgroups per CU (register limit)
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag); }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
   // region row pitch in 64-bit words: odd, so the rows of a member patch
   // spread over the LDS banks
   static __host__ __device__ int pitch(int rw) { return rw | 1; }
-  static __host__ __device__ size_t per_wave(int S, int T) {
+  static __host__ __device__ size_t region(int S, int T) {
     return (size_t)rnum(S, T) * pitch(rnum(S, T)) * sizeof(int64_t);
   }
-  // waves per workgroup: as many as the LDS holds (0: the tile does not fit)
-  static __host__ __device__ int waves(int S, int T) {
-    const size_t t = tables(), pw = per_wave(S, T);
-    const size_t n = t >= kLdsBytes ? 0 : (kLdsBytes - t) / pw;
-    return n > (size_t)kMaxWaves ? kMaxWaves : (int)n;
-  }
-  static __host__ __device__ size_t bytes(int S, int T) {
-    const int nw = waves(S, T);
-    return nw == 0 ? kLdsBytes + 1 : tables() + (size_t)nw * per_wave(S, T);
-  }
+  // tables, region, then the reference counter and the tile index
+  static __host__ __device__ size_t bytes(int S, int T) { return tables() + region(S, T) + 16; }
+  // waves per workgroup (0: the tile does not fit)
+  static __host__ __device__ int waves(int S, int T) { return bytes(S, T) <= kLdsBytes ? kWaves : 0; }
 };
 
 __host__ __device__ inline size_t filter_lds_bytes(int xform, int S, int T) {
@@ -898,28 +899,23 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
   }
 }
 
+// One wave's part of a reference tile (geometry g): references drawn from
+// the workgroup's counter *lctr until the tile is exhausted.
 template <int STEP, class XF>
-__device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
+__device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const BlockGeom& g, int ch,
                                  const typename XF::frag* __restrict__ tabB,
-                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg) {
+                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg, int* lctr) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
-  const int S = STEP == 1 ? kp.S1 : kp.S2;
   const int nmax = STEP == 1 ? kp.n1 : kp.n2;
   const int32_t* __restrict__ idx = STEP == 1 ? d.idx1 : d.idx2;
   const int32_t* __restrict__ cnt = STEP == 1 ? d.cnt1 : d.cnt2;
-  const int T = kp.tile;
   const int h = d.h, w = d.w;
   const size_t hw = (size_t)h * w;
   const int l = lane_id();
   const int q = l >> 4, col = l & 15;
-  const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, T, ty, tx);
-  const int RH = g.ny + 7, RW = g.nx + 7;  // numerator region (pixels)
-  const int RP = C::pitch(RW);             // its row pitch (64-bit words)
+  const int RP = C::pitch(g.nx + 7);  // the region's row pitch (64-bit words)
   int64_t* __restrict__ gwsum = d.wsum + ch * hw;
-
-  for (int i = l; i < RH * RP; i += 64) wreg[i] = 0;
-  wave_lds_sync();
 
   const float centre = channel_centre(d.c, ch);
   const float* __restrict__ noisy = d.planar + ch * hw;
@@ -935,31 +931,30 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
   // loaded while the previous reference is inverted and aggregated (slots
   // beyond the group hold -1 and are ignored below).  Step 2 issues the
   // loads of its basic pixels before the noisy transform, which hides them.
-  // The tile's references in row-major order, by global index: walked with
-  // counters (an integer division on the scalar unit costs tens of
-  // instructions).  One walk for the prefetch, one for the current reference.
-  size_t r_pf = (size_t)g.ri0 * d.nc + g.ci0, r_cur = r_pf;
-  int c_pf = 0, c_cur = 0;
-  auto advance = [&](size_t& r, int& c) {
-    if (++c == g.nci) {
-      c = 0;
-      r += d.nc - g.nci + 1;
-    } else {
-      r++;
-    }
+  // References come from the workgroup's counter (row-major within the
+  // tile), one draw per reference, two ahead of their use.
+  auto draw = [&]() {
+    int k = 0;
+    if (l == 0) k = __hip_atomic_fetch_add(lctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_amdgcn_readfirstlane(k);
   };
+  int k_pf = draw();   // the reference whose slots are (to be) prefetched
+  size_t r_nx = 0;     // its global index
   int cnt_nx = 0, gi_nx[2] = {-1, -1};
-  auto prefetch = [&]() {  // the next reference not yet prefetched
-    const size_t rn = r_pf;
-    advance(r_pf, c_pf);
+  auto prefetch = [&]() {  // the slots of reference k_pf < nrefs
+    const int a = k_pf / g.nci;
+    const size_t rn = (size_t)(g.ri0 + a) * d.nc + g.ci0 + (k_pf - a * g.nci);
+    r_nx = rn;
     cnt_nx = ldg(cnt + rn);
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) gi_nx[gt] = ldg(idx + rn * nmax + (16 * gt + col < nmax ? 16 * gt + col : 0));
   };
   int n_nx = 1, my_nx[2], mx_nx[2];
   bool mv_nx[2];
+  size_t r_st = 0;  // global index of the staged reference
   f32x4 an[2][4];  // noisy member pixels of the next reference
   auto stage = [&]() {
+    r_st = r_nx;
     // group size and everything derived from it are wave-uniform
     n_nx = __builtin_amdgcn_readfirstlane(min(max(cnt_nx, 1), nmax));
 #pragma unroll
@@ -988,14 +983,16 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       }
     }
   };
-  if (nrefs > 0) {
+  bool have = k_pf < nrefs;
+  if (have) {
     prefetch();
     stage();
-    if (nrefs > 1) prefetch();
+    k_pf = draw();
+    if (k_pf < nrefs) prefetch();
   }
-  for (int j = 0; j < nrefs; j++) {
-    const size_t r = r_cur;
-    advance(r_cur, c_cur);
+  while (have) {
+    const size_t r = r_st;
+    bool have_next = false;
     // the group size and everything derived from it are wave-uniform (kept
     // in scalar registers: the transforms branch on them)
     const int n = __builtin_amdgcn_readfirstlane(n_nx);
@@ -1158,9 +1155,11 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
       }
     }
     // the next reference's positions and noisy pixels, then slots two ahead
-    if (j + 1 < nrefs) {
+    have_next = k_pf < nrefs;
+    if (have_next) {
       stage();
-      if (j + 2 < nrefs) prefetch();
+      k_pf = draw();
+      if (k_pf < nrefs) prefetch();
     }
     // ---- inverse 2-D DCT (the Kaiser weight of each output pixel is folded
     // into the table), exact accumulation into the wave's region.  Lane
@@ -1191,25 +1190,47 @@ __device__ void filter_wave_tile(const ImgDesc& d, const KParams& kp, int ty, in
     };
     if (n > 16) group(std::integral_constant<int, 2>());
     else group(std::integral_constant<int, 1>());
+    have = have_next;
   }
+}
 
-  // ---- flush: the region into num, four rows per iteration (all their LDS
-  // reads first); pixels no member touched hold exact zeros and are skipped
-  wave_lds_sync();
-  int64_t* gnum = d.num + ch * hw;
-  for (int x0 = 0; x0 < RW; x0 += 64) {
-    const int x = x0 + l;
-    const int xc = min(x, RW - 1);  // in-range address for lanes past the region
-    for (int y0 = 0; y0 < RH; y0 += 4) {
-      int64_t nv[4];
+// A workgroup's reference tile (ty, tx) of channel ch: its waves filter the
+// tile's references into the shared region, then the region is added into
+// num, two rows per wave and iteration (pixels no member touched hold exact
+// zeros and are skipped), and cleared for the next tile together with the
+// reference counter.  The region and counter must be zero on entry.
+template <int STEP, class XF>
+__device__ void filter_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
+                            const typename XF::frag* tabB, const typename XF::frag* tabA, int64_t* wreg,
+                            int* lctr) {
+  typedef FilterCfg<XF> C;
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
+  const BlockGeom g = block_geom(d.h, d.w, d.nr, d.nc, S, kp.tile, ty, tx);
+  filter_tile_refs<STEP, XF>(d, kp, g, ch, tabB, tabA, wreg, lctr);
+  __syncthreads();
+  const int RH = g.ny + 7, RW = g.nx + 7, RP = C::pitch(RW);
+  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, l = lane_id();
+  int64_t* gnum = d.num + (size_t)ch * d.h * d.w;
+  for (int y0 = 2 * wave; y0 < RH; y0 += 2 * nw) {
+    for (int x = l; x < RW; x += 64) {
+      int64_t nv[2];
 #pragma unroll
-      for (int k = 0; k < 4; k++) nv[k] = wreg[min(y0 + k, RH - 1) * RP + xc];
+      for (int k = 0; k < 2; k++) nv[k] = y0 + k < RH ? wreg[(y0 + k) * RP + x] : 0;
 #pragma unroll
-      for (int k = 0; k < 4; k++)
-        if (y0 + k < RH && x < RW && nv[k] != 0) gadd_i64(gnum + (size_t)(g.uy0 + y0 + k) * w + g.ux0 + x, nv[k]);
+      for (int k = 0; k < 2; k++)
+        if (nv[k] != 0) {
+          gadd_i64(gnum + (size_t)(g.uy0 + y0 + k) * d.w + g.ux0 + x, nv[k]);
+          wreg[(y0 + k) * RP + x] = 0;
+        }
     }
   }
-  wave_lds_sync();
+  if (threadIdx.x == 0) *lctr = 0;
+  __syncthreads();
+}
+
+// zero the region and the control words of a filter workgroup
+__device__ inline void filter_lds_clear(int64_t* wreg, size_t region_bytes) {
+  for (size_t i = threadIdx.x; i < region_bytes / 8 + 2; i += blockDim.x) wreg[i] = 0;
 }
 
 // One workgroup = as many waves as the LDS holds (blockDim.x / 64), each on
@@ -1218,16 +1239,17 @@ template <int STEP, class XF>
 __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch, char* smem) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
+  int64_t* wreg = (int64_t*)(smem + C::tables());
+  const size_t rb = C::region(S, kp.tile);
   filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
+  filter_lds_clear(wreg, rb);
   __syncthreads();
-  const int S = STEP == 1 ? kp.S1 : kp.S2;
-  const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int64_t* wreg = (int64_t*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
-  const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
-  const int t = blockIdx.x * nw + wave;
-  if (t < ntx * nty) filter_wave_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg);
+  const int ntx = (d.nc + kp.tile - 1) / kp.tile;
+  const int t = blockIdx.x;
+  filter_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg, (int*)(wreg + rb / 8));
 }
 
 // image holding global item i: largest k with prefix[k] <= i
@@ -1244,38 +1266,42 @@ template <int STEP, class XF>
 __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
+  const int S = STEP == 1 ? kp.S1 : kp.S2;
   frag* tabB = (frag*)smem;
   frag* tabA = tabB + 16 * 64;
+  int64_t* wreg = (int64_t*)(smem + C::tables());
+  const size_t rb = C::region(S, kp.tile);
+  int* lctl = (int*)(wreg + rb / 8);  // reference counter, tile index
   filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
+  filter_lds_clear(wreg, rb);
   __syncthreads();
-  const int S = STEP == 1 ? kp.S1 : kp.S2;
-  // the work index is wave-uniform, so the descriptor below is read once
-  // with scalar loads and kept in registers (a reference into global memory
-  // would be re-read after every store the compiler cannot disambiguate)
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
-  int64_t* wreg = (int64_t*)(smem + C::tables() + wave * C::per_wave(S, kp.tile));
-  // With a counter, tiles go to waves as they become free (tile costs vary
-  // with group sizes and image edges, and a workgroup holds its LDS until
-  // its last wave ends); one atomic per tile, against the tile's ~10^5
-  // cycles, all lanes taking part with lane 0 adding 1.  Without one, wave w
-  // of workgroup b takes every (gridDim.x * nw)-th tile from b * nw + w.
-  const int l = lane_id();
+  // With a counter, tiles go to workgroups as they become free (tile costs
+  // vary with group sizes and image edges); one atomic per tile, against the
+  // tile's ~10^6 cycles.  Without one, workgroup b takes every gridDim.x-th
+  // tile from b.
   const bool dyn = br.ctr != nullptr;
-  const int total = br.end - br.begin, stride = gridDim.x * nw;
-  int t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : blockIdx.x * nw + wave);
-  while (t < total) {
+  const int total = br.end - br.begin;
+  int t = blockIdx.x;
+  while (true) {
+    if (threadIdx.x == 0) lctl[1] = dyn ? atomicAdd(br.ctr, 1) : t;
+    __syncthreads();
+    // the work index is uniform, so the descriptor below is read once with
+    // scalar loads and kept in registers (a reference into global memory
+    // would be re-read after every store the compiler cannot disambiguate)
+    t = __builtin_amdgcn_readfirstlane(lctl[1]);
+    if (t >= total) break;
     const int i = br.begin + t;
     const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
     const ImgDesc d = ldc(br.ds + im);
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
-    filter_wave_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg);
-    t = __builtin_amdgcn_readfirstlane(dyn ? atomicAdd(br.ctr, l == 0 ? 1 : 0) : t + stride);
+    filter_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl);
+    t += gridDim.x;
   }
-  // every wave has drawn an index past the end; the last one to get here
-  // zeroes the pair for the next launch
-  if (dyn && l == 0 && atomicAdd(br.ctr + 1, 1) == (int)gridDim.x * nw - 1) {
+  // every workgroup has drawn an index past the end; the last one to get
+  // here zeroes the pair for the next launch
+  if (dyn && threadIdx.x == 0 && atomicAdd(br.ctr + 1, 1) == (int)gridDim.x - 1) {
     atomicExch(br.ctr, 0);
     atomicExch(br.ctr + 1, 0);
   }
@@ -1302,7 +1328,8 @@ __global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
   match2_block(d, kp, blockIdx.y, blockIdx.x, smem);
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kMaxWaves) k_filter(ImgDesc d, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) __attribute__((amdgpu_waves_per_eu(2)))
+k_filter(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
 }
@@ -1363,7 +1390,8 @@ kb_match(BatchRef br, KParams kp) {
   }
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kMaxWaves) kb_filter(BatchRef br, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) __attribute__((amdgpu_waves_per_eu(2)))
+kb_filter(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_batch<STEP, XF>(br, kp, smem);
 }
@@ -1433,7 +1461,7 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
       const int nw = filter_waves(xform, S, kp.tile);
       if (nw < 1) return -1;
       const int ntiles = ((d.nc + kp.tile - 1) / kp.tile) * ((d.nr + kp.tile - 1) / kp.tile);
-      dim3 grid((ntiles + nw - 1) / nw, d.c);
+      dim3 grid(ntiles, d.c);
       size_t b = filter_lds_bytes(xform, S, kp.tile);
 #define LAUNCH_F(STEP, XF)                                                                \
   do {                                                                                    \
@@ -1499,10 +1527,10 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
       const int wv = filter_waves(xform, S, kp.tile);
       if (wv < 1) return -1;
       size_t b = filter_lds_bytes(xform, S, kp.tile);
-      int g = blocks > 0 ? std::min(blocks, (nw + wv - 1) / wv) : (nw + wv - 1) / wv;
+      int g = blocks > 0 ? std::min(blocks, nw) : nw;
       // dynamic tiles: as many workgroups as fit on the device at once
       if (br.ctr && cus > 0)
-        g = std::min((nw + wv - 1) / wv, cus * std::max(1, (int)(163840 / b)));
+        g = std::min(nw, cus * std::max(1, std::min(FilterCfg<XF32>::kPerCU, (int)(kLdsBytes / b))));
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
     lds_attr(kb_filter<STEP, XF>, b);                                                     \

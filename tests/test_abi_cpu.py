@@ -231,7 +231,7 @@ def test_host_validation_rejects_before_enqueue(B):
         setattr(q, field, val)
         assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(q), fake, None) == -1, field
     big = p.copy()
-    big.tile_refs = 16  # the largest tile: fewer waves per workgroup, but it fits the LDS
+    big.tile_refs = 16  # the largest tile: its region still fits the LDS
     assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(big), fake, None) == -3  # (then: no workspace)
     # a Kaiser window so sharp that the FP32 corner weights approach underflow
     sharp = p.copy()

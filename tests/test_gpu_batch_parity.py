@@ -29,7 +29,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 oracle.set_threads(16)
-TILE = 5  # the filter tile the autotuner picks for this workload on MI355X
+TILE = 10  # the filter tile (references per workgroup side) the autotuner picks here
 
 
 @pytest.fixture(scope="module")
@@ -112,7 +112,7 @@ def test_mixed_batch_step1_bit_exact(B):
     plan.close()
 
 
-@pytest.mark.parametrize("tile", [4, 5])
+@pytest.mark.parametrize("tile", [8, 10])
 def test_bench_config_step1_bit_exact(B, tile):
     samples = bench16()
     plan, *_ = make_plan(B, samples, xform=1, tile=tile)
