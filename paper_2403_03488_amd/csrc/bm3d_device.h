@@ -118,10 +118,15 @@ constexpr float kMaxWeight = 1024.f;
 // 1.5 * 2^52: for |v 2^FRAC| < 2^51 the sum keeps the rounded value in its
 // low mantissa bits, read out by an integer subtraction (4 instructions
 // instead of a generic float-to-int64 conversion).
-template <int FRAC> __device__ inline int64_t to_fix(float v) {
+// round(v) as a 64-bit integer, for |v| < 2^51: adding 1.5 * 2^52 in double
+// leaves the rounded value in the low mantissa bits (the constant's low word
+// is zero, so only the high word is corrected)
+__device__ inline int64_t round_i64(float v) {
   const double magic = 6755399441055744.0;  // 1.5 * 2^52
-  const double t = __builtin_fma((double)v, (double)(1ull << FRAC), magic);
-  return __double_as_longlong(t) - __double_as_longlong(magic);
+  return __double_as_longlong((double)v + magic) - __double_as_longlong(magic);
+}
+template <int FRAC> __device__ inline int64_t to_fix(float v) {
+  return round_i64(v * (float)(1ull << FRAC));  // exact scaling by a power of two
 }
 template <int FRAC> __device__ inline float from_fix(int64_t n) {
   return (float)((double)n * (1.0 / (double)(1ull << FRAC)));
@@ -455,6 +460,8 @@ typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 // in the same slots of both operands gives the same sum whatever order the
 // hardware assigns to the 32 contraction indices.
 struct XF32 {
+  // the inverse table can carry the fixed-point scale 2^kNumFrac (FP32 range)
+  static constexpr bool kScaledInverse = true;
   typedef f32x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return a; }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
@@ -469,6 +476,8 @@ struct XF32 {
   }
 };
 struct XBF16 {
+  // the inverse table can carry the fixed-point scale 2^kNumFrac (FP32 exponent range)
+  static constexpr bool kScaledInverse = true;
   typedef bf16x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
@@ -482,6 +491,8 @@ struct XBF16 {
   }
 };
 struct XF16 {
+  // the inverse table can carry the fixed-point scale 2^kNumFrac (2^28 overflows FP16)
+  static constexpr bool kScaledInverse = false;
   typedef f16x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {

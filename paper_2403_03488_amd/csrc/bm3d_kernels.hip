@@ -819,13 +819,15 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 // the per-position sum of group weights, so the filter adds each member's
 // weight once, at its corner, into a global weight map (wsum); the
 // aggregation forms the denominator from it.
-// Four waves per workgroup and two workgroups per CU (the filters hold up
-// to 256 registers per lane): while one workgroup waits for its slowest wave
-// or flushes, the other keeps the SIMDs busy.
+// Four waves per workgroup and two or three workgroups per CU: while one
+// workgroup waits for its slowest wave or flushes, the others keep the SIMDs
+// busy.
 template <class XF> struct FilterCfg {
   typedef typename XF::frag frag;
   static constexpr int kWaves = 4;   // waves per workgroup
-  static constexpr int kPerCU = 2;   // workgroups per CU (register limit)
+  // workgroups per CU the registers allow: step 1 in a 16-bit form fits 168
+  // registers per lane (3 waves per SIMD), the others need up to 256
+  static constexpr int per_cu(int step) { return step == 1 && sizeof(frag) == 8 ? 3 : 2; }
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag); }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
   // region row pitch in 64-bit words: odd, so the rows of a member patch
@@ -865,7 +867,8 @@ __device__ inline typename XF::frag had_frag(int rt, int kt, int n) {
 
 // Builds the two fragment tables of a workgroup's 2-D transform (caller
 // synchronises): forward B[pix][coef] = F[a][u] F[b][v] and inverse
-// A[pix][coef] = I[u][a] I[v][b] K(u) K(v), coef = (a, b), pix = (u, v), each
+// A[pix][coef] = I[u][a] I[v][b] K(u) K(v) (times 2^kNumFrac where the form
+// allows), coef = (a, b), pix = (u, v), each
 // product formed in double and rounded once (the rational entries -- the
 // 2-D mean's 1/8, and bior1.5's 1/4 and 1/2 -- are then exact).
 template <class XF>
@@ -886,9 +889,12 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
         coef = 16 * (f & 3) + 4 * lq + v;
       }
       const int a = coef >> 3, b = coef & 7, u = pix >> 3, vv = pix & 7;
-      // the inverse table carries the Kaiser weight of its output pixel
+      // the inverse table carries the Kaiser weight of its output pixel and,
+      // where the form's range allows, the fixed-point scale of the
+      // accumulators (a power of two: exact)
       v4[v] = tab == 0 ? (float)(F[a * 8 + u] * F[b * 8 + vv])
-                       : (float)(I[u * 8 + a] * I[vv * 8 + b] * (double)kaiser[u] * (double)kaiser[vv]);
+                       : (float)(I[u * 8 + a] * I[vv * 8 + b] * (double)kaiser[u] * (double)kaiser[vv] *
+                                 (XF::kScaledInverse ? (double)(1ull << kNumFrac) : 1.0));
     }
     // stored so that the two tiles of one 32-deep contraction step are
     // adjacent for each lane: B at ((kt/2)*4 + nt, lane, kt%2), A at
@@ -1183,7 +1189,8 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
         }
         int64_t* rr = rb + 2 * mt * RP;
 #pragma unroll
-        for (int v = 0; v < 4; v++) lds_add_i64(rr + v, to_fix<kNumFrac>(acc[v]));
+        for (int v = 0; v < 4; v++)
+          lds_add_i64(rr + v, XF::kScaledInverse ? round_i64(acc[v]) : to_fix<kNumFrac>(acc[v]));
       }
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
     }
@@ -1328,8 +1335,8 @@ __global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
   match2_block(d, kp, blockIdx.y, blockIdx.x, smem);
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) __attribute__((amdgpu_waves_per_eu(2)))
-k_filter(ImgDesc d, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves)
+__attribute__((amdgpu_waves_per_eu(FilterCfg<XF>::per_cu(STEP)))) k_filter(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
 }
@@ -1390,8 +1397,8 @@ kb_match(BatchRef br, KParams kp) {
   }
 }
 template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves) __attribute__((amdgpu_waves_per_eu(2)))
-kb_filter(BatchRef br, KParams kp) {
+__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves)
+__attribute__((amdgpu_waves_per_eu(FilterCfg<XF>::per_cu(STEP)))) kb_filter(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   filter_block_batch<STEP, XF>(br, kp, smem);
 }
@@ -1530,7 +1537,8 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
       int g = blocks > 0 ? std::min(blocks, nw) : nw;
       // dynamic tiles: as many workgroups as fit on the device at once
       if (br.ctr && cus > 0)
-        g = std::min(nw, cus * std::max(1, std::min(FilterCfg<XF32>::kPerCU, (int)(kLdsBytes / b))));
+        g = std::min(nw, cus * std::max(1, std::min(stage == STAGE_FILTER1 && xform != 0 ? 3 : 2,
+                                                    (int)(kLdsBytes / b))));
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
     lds_attr(kb_filter<STEP, XF>, b);                                                     \
