@@ -125,6 +125,12 @@ __device__ inline int64_t round_i64(float v) {
   const double magic = 6755399441055744.0;  // 1.5 * 2^52
   return __double_as_longlong((double)v + magic) - __double_as_longlong(magic);
 }
+// round(v s) as a 64-bit integer, for |v s| < 2^51: the double FMA rounds
+// the exact product once, into the magic number's low mantissa bits
+__device__ inline int64_t round_scaled_i64(float v, double s) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  return __double_as_longlong(__builtin_fma((double)v, s, magic)) - __double_as_longlong(magic);
+}
 template <int FRAC> __device__ inline int64_t to_fix(float v) {
   return round_i64(v * (float)(1ull << FRAC));  // exact scaling by a power of two
 }

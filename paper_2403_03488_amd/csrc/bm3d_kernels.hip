@@ -1145,19 +1145,24 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
     }
     if (l == 0) D2[0][0][0] -= off;
 
-    // ---- inverse WHT, with this lane's member weight (0 if absent) folded in
-    float wm[2];
+    // ---- inverse WHT.  This lane's member weight (0 if absent) and the
+    // WHT's 1/n are applied in the fixed-point rounding below, in double
+    // (one rounding of the product); the FP16 form takes the 1/n (exact)
+    // before its conversion, for range.
+    constexpr bool kRangeScale = !XF::kScaledInverse;
+    double wm[2];
 #pragma unroll
-    for (int gt = 0; gt < 2; gt++) wm[gt] = mv[gt] ? wgt : 0.f;
+    for (int gt = 0; gt < 2; gt++)
+      wm[gt] = mv[gt] ? (kRangeScale ? (double)wgt * (double)(1ull << kNumFrac) : (double)(rn * wgt)) : 0.0;
     f32x4 D3[4][2];
 #pragma unroll
     for (int ct = 0; ct < 4; ct++) {
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
-        const f32x4 acc = NG == 2 ? XF::mma2(XF::cvt(D2[0][ct]), XF::cvt(D2[1][ct]), Hf[gt][0], Hf[gt][1], zero4())
-                                  : XF::mma(XF::cvt(D2[0][ct]), Hf[gt][0], zero4());
-        D3[ct][gt] = acc * (rn * wm[gt]);
+        D3[ct][gt] = NG == 2 ? XF::mma2(XF::cvt(D2[0][ct]), XF::cvt(D2[1][ct]), Hf[gt][0], Hf[gt][1], zero4())
+                             : XF::mma(XF::cvt(D2[0][ct]), Hf[gt][0], zero4());
+        if (kRangeScale) D3[ct][gt] *= rn;
       }
     }
     // the next reference's positions and noisy pixels, then slots two ahead
@@ -1189,8 +1194,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
         }
         int64_t* rr = rb + 2 * mt * RP;
 #pragma unroll
-        for (int v = 0; v < 4; v++)
-          lds_add_i64(rr + v, XF::kScaledInverse ? round_i64(acc[v]) : to_fix<kNumFrac>(acc[v]));
+        for (int v = 0; v < 4; v++) lds_add_i64(rr + v, round_scaled_i64(acc[v], wm[gt]));
       }
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
     }
