@@ -788,11 +788,6 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 }
 
 // ========================================================= collaborative ==
-// Each wave filters the groups of its own T x T tile of references and
-// aggregates them into a wave-private LDS accumulator covering the tile's
-// search region; the region is then added into num with one coalesced
-// atomic per touched pixel.  A workgroup only shares the transform tables.
-//
 // Per group (n members, one channel), with the 16x16 fragments of
 // bm3d_device.h (g = member, t = Hadamard index, pix = 8x8 pixel, coef = 8x8
 // DCT coefficient, CC[coef][pix] = C[a][u] C[b][v]):
