@@ -991,7 +991,12 @@ def main():
             "unit": unit, "frac": achieved / peak,
             "traffic": measured_traffic(dom, B, p.tile_refs) if args.xform == "bf16" else None,
             "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom],
-            "work_model": "separable 3-D transforms at the actual group sizes (2 ops per multiply-add)"}
+            "work_model": {"match1": "S^2 * 64 int8 multiply-adds per reference",
+                           "match2": "S^2 * 64 FP32 multiply-adds per reference (direct differences)",
+                           "filter1": "separable 3-D transforms at the actual group sizes, 2048n + 128n^2 "
+                                      "multiply-adds per group and channel",
+                           "filter2": "separable 3-D transforms at the actual group sizes, 3 (1024n + 64n^2) "
+                                      "multiply-adds per group and channel"}[dom] + " (2 ops per multiply-add)"}
     if dom in issued:
         roof["mfma_issued"] = {"ops_per_launch": issued[dom],
                                "TOPps": issued[dom] / (stage_ms[dom] * 1e-3) / 1e12,
