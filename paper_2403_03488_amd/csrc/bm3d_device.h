@@ -306,11 +306,21 @@ __device__ inline void wave_lds_sync() {
 // least k values are <= the result).  Radix descent: bit by bit from the top,
 // a bit of the k-th smallest is 0 iff at least k values are <= the largest
 // number with the bits found so far and a 0 there.  NV vector compares per
-// bit; the counts and the prefix stay on the scalar unit.
-template <int LO, int NV> __device__ inline uint32_t wave_kth_u32(const uint32_t (&v)[NV], int k) {
+// bit; the counts and the prefix stay on the scalar unit.  Bits above hi
+// (wave-uniform) are taken as 0: the caller knows every value of interest
+// is below 2^(hi+1), and larger ones only raise the bound to all ones.
+template <int LO, int NV> __device__ inline uint32_t wave_kth_u32(const uint32_t (&v)[NV], int k, int hi = 31) {
   uint32_t prefix = 0;
+  if (hi < 31) {  // does the k-th smallest have a bit set above hi?
+    const uint32_t t = (2u << hi) - 1u;
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NV; i++) c += __popcll(__ballot(v[i] <= t));
+    if (c < k) return ~0u;
+  }
 #pragma unroll
   for (int bit = 31; bit >= LO; bit--) {
+    if (bit > hi) continue;
     const uint32_t t = prefix | ((1u << bit) - 1u);
     int c = 0;
 #pragma unroll
@@ -337,10 +347,22 @@ template <class K> __device__ inline void two_smallest(const K (&k)[16], K& m1, 
 // (distance, window index).  n[r] = largest power of two <= min(1 +
 // #candidates, nmax); lanes 0..n-2 receive the n-1 smallest keys in
 // ascending order in sel[r].  buf[r] is wave-private LDS scratch of at least
-// as many entries as there are candidates (may alias the keys' source).
-template <class K, int NR>
-__device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR], K (&sel)[NR],
-                             int (&n)[NR]) {
+// as many entries as there are candidates, plus 64 spare entries from
+// buf[r] + spare (may alias the keys' source).  Keys of candidates are below
+// 2^(hi+1) (wave-uniform).
+//
+// theta = an upper bound of the (nmax-1)-th smallest key: the (nmax-1)-th
+// smallest lane minimum (nmax-1 distinct candidates lie at or below it),
+// from a radix descent over the key bits above LO (the window index and the
+// low distance bits are left set: a coarser bound only admits a few more
+// survivors, which the sort orders anyway).  If it exists, at least nmax-1
+// candidates pass and n = nmax without a count; otherwise the passing
+// candidates are counted and all of them survive.  Survivors (key <= theta)
+// are compacted into buf by ballot (the others store to a spare entry of
+// their own, so no store is branched around), then sorted.
+template <class K, int NR, int LO>
+__device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR], int spare, int hi,
+                             K (&sel)[NR], int (&n)[NR]) {
   static_assert(sizeof(K) == 4, "keys are distance << 10 | window index");
   const K NONE = ~(K)0;
   const int l = lane_id();
@@ -349,19 +371,18 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < NR; r++) {
-    int npass = 0;
-#pragma unroll
-    for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[r][t] != NONE));
-    const int m = 1 + npass < nmax ? 1 + npass : nmax;
-    n[r] = 1 << (31 - __clz(m));
-    // Upper bound on the (n-1)-th smallest key: the (n-1)-th smallest of the
-    // lane minima (n-1 distinct candidates lie at or below it), exact in the
-    // distance bits.  The callers spread window-adjacent candidates over
-    // lanes, so one minimum per lane already bounds tightly.
     uint32_t mn[1] = {k[r][0]};
 #pragma unroll
     for (int t = 1; t < 16; t++) mn[0] = kmin(mn[0], k[r][t]);
-    theta[r] = n[r] > 1 ? wave_kth_u32<10, 1>(mn, n[r] - 1) : (K)0;
+    theta[r] = nmax > 1 ? wave_kth_u32<LO, 1>(mn, nmax - 1, hi) : (K)0;
+    n[r] = nmax;
+    if (nmax > 1 && theta[r] == NONE) {  // fewer than nmax-1 lanes hold a candidate
+      int npass = 0;
+#pragma unroll
+      for (int t = 0; t < 16; t++) npass += __popcll(__ballot(k[r][t] != NONE));
+      const int m = 1 + npass < nmax ? 1 + npass : nmax;
+      n[r] = 1 << (31 - __clz(m));
+    }
     base[r] = 0;
   }
   // compact the survivors (candidates with key <= theta) into buf
@@ -371,7 +392,7 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
     for (int r = 0; r < NR; r++) {
       const bool p = n[r] > 1 && k[r][t] <= theta[r] && k[r][t] != NONE;
       const uint64_t b = __ballot(p);
-      if (p) buf[r][base[r] + __popcll(b & lt)] = k[r][t];
+      buf[r][p ? base[r] + __popcll(b & lt) : spare + l] = k[r][t];
       base[r] += __popcll(b);
     }
   }
@@ -400,40 +421,46 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
 // Step-2 variant on FP32 distances.  db[t] = bit pattern of a non-negative
 // distance (~0u = not a candidate), wi[t] = its window index; the order is
 // (distance, window index) as 64-bit keys (bits << 32 | index).  The bound
-// theta is taken on the distances' top 22 bits (monotone in the distance):
-// the (n-1)-th smallest among the lanes' two smallest truncated distances.
-// Every candidate whose truncated distance does not exceed theta survives: a
-// candidate above it has n-1 others with strictly smaller distances, so it
-// cannot be among the n-1 smallest.  Only the survivors are sorted on full
-// 64-bit keys.  Result as select_group.
+// theta is taken on the distances' top 16 bits (monotone in the distance,
+// 2^-7 relative): the (nmax-1)-th smallest among the lanes' two smallest
+// truncated distances.  Every candidate whose truncated distance does not
+// exceed theta survives: a candidate above it has nmax-1 others with
+// strictly smaller distances, so it cannot be among the n-1 smallest.  If
+// the bound does not exist, fewer than nmax-1 candidates pass: they are
+// counted and all survive.  Only the survivors are sorted on full 64-bit
+// keys.  buf holds at least as many entries as there are candidates, plus 64
+// spare entries from buf + spare.  Result as select_group.
 __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t (&wi)[16], int nmax,
-                                       uint64_t* buf, uint64_t& sel) {
+                                       uint64_t* buf, int spare, uint64_t& sel) {
   const uint32_t NONE = ~0u;
   const int l = lane_id();
-  int npass = 0;
-#pragma unroll
-  for (int t = 0; t < 16; t++) npass += __popcll(__ballot(db[t] != NONE));
-  int m = 1 + npass < nmax ? 1 + npass : nmax;
-  int n = 1 << (31 - __clz(m));
   sel = ~0ull;
-  if (n == 1) return 1;
-  const int want = n - 1;
-  // bound on the truncated distances (top 22 bits): the want-th smallest of
-  // the lanes' two smallest (a lane holds 16 window-adjacent candidates,
-  // which are often similar), so at least want candidates survive
-  uint32_t tk[16];
-#pragma unroll
-  for (int t = 0; t < 16; t++) tk[t] = db[t] | 0x3FFu;
+  if (nmax < 2) return 1;
+  int n = nmax;
+  // bound on the truncated distances: the (nmax-1)-th smallest of the lanes'
+  // two smallest (a lane holds 16 window-adjacent candidates, which are
+  // often similar)
+  // (min and max commute with setting the low bits)
   uint32_t m2[2];
-  two_smallest<uint32_t>(tk, m2[0], m2[1]);
-  const uint32_t th = wave_kth_u32<10, 2>(m2, want) >> 10;
+  two_smallest<uint32_t>(db, m2[0], m2[1]);
+  m2[0] |= 0xFFFFu;
+  m2[1] |= 0xFFFFu;
+  const uint32_t th = wave_kth_u32<16, 2>(m2, nmax - 1) >> 16;
+  if (th == (NONE >> 16)) {  // fewer than nmax-1 candidates
+    int npass = 0;
+#pragma unroll
+    for (int t = 0; t < 16; t++) npass += __popcll(__ballot(db[t] != NONE));
+    const int m = 1 + npass < nmax ? 1 + npass : nmax;
+    n = 1 << (31 - __clz(m));
+    if (n == 1) return 1;
+  }
   int base = 0;
   const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int t = 0; t < 16; t++) {
-    bool p = db[t] != NONE && (db[t] >> 10) <= th;
-    uint64_t b = __ballot(p);
-    if (p) buf[base + __popcll(b & lt)] = ((uint64_t)db[t] << 32) | wi[t];
+    const bool p = db[t] != NONE && (db[t] >> 16) <= th;
+    const uint64_t b = __ballot(p);
+    buf[p ? base + __popcll(b & lt) : spare + l] = ((uint64_t)db[t] << 32) | wi[t];
     base += __popcll(b);
   }
   wave_lds_sync();

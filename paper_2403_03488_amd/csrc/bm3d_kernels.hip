@@ -205,16 +205,20 @@ __device__ inline BlockGeom block_geom(int h, int w, int nr, int nc, int S, int 
 
 // =========================================================== step-1 match ==
 // LDS: int8 luminance region [(S+16) rows][64 B used of kM1Pitch],
-// candidate norms [(S+9)][48] int32, keys of one pass [8 refs][S*S+8]
-// uint32 (also row-sum scratch).  The 16 references of a block are matched in two passes of 8
+// candidate norms [(S+9)][48] int32, keys of one pass [8 refs][S*S+72]
+// uint32 (also row-sum scratch; the last 64 slots of a reference are the
+// selection's spare entries).  The 16 references of a block are matched in two passes of 8
 // (reference columns 0-1, then 2-3), which halves the key buffer so that
 // three blocks fit a CU.
 // Row pitches are padded against LDS bank conflicts: region rows 80 B apart
 // (the four lane groups of a fragment read rows 2 apart, 40 dwords = 8 banks
-// mod 32), and per-reference key slots S*S+8 apart (lane groups store to
+// mod 32), and per-reference key slots S*S+72 apart (lane groups store to
 // references 2 apart, 16 banks mod 32).
 constexpr int kM1Passes = 2, kM1PassRefs = 16 / kM1Passes, kM1Pitch = 80;
-__host__ __device__ inline int match1_key_stride(int S) { return S * S + 8; }
+__host__ __device__ inline int match1_key_stride(int S) { return S * S + 72; }
+// the selection's radix bound stops above this bit (distance bits below it:
+// 64 SSD units, a few more survivors at most)
+constexpr int kM1SelLo = 16;
 __host__ __device__ inline size_t match1_lds_bytes(int S) {
   size_t keys = (size_t)kM1PassRefs * match1_key_stride(S) * 4, rs = (size_t)(S + 16) * 48 * 4;
   return (size_t)(S + 16) * kM1Pitch + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
@@ -335,6 +339,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     mnp[v] = nq[(ry - g.uy0) * 48 + (rx - g.ux0)];
   }
   const uint32_t thr = d.thr1;
+  // highest bit a candidate's key (distance << 10 | window index) can have
+  const int key_top = thr >= (1u << 22) ? 31 : 31 - __clz((thr << 10) | 1023u);
   const int wv = __builtin_amdgcn_readfirstlane(wave);
 
 #pragma unroll
@@ -421,7 +427,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
       }
       uint32_t sel[2];
       int n[2];
-      select_group<uint32_t, 2>(k, nmax, buf, sel, n);
+      select_group<uint32_t, 2, kM1SelLo>(k, nmax, buf, S * S, key_top, sel, n);
 #pragma unroll
       for (int r = 0; r < 2; r++) {
         if (!act[r]) continue;
@@ -455,7 +461,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 constexpr int kM2Pitch = 49;
 __host__ __device__ inline size_t match2_lds_bytes(int S, int nwaves) {
   size_t regb = ((size_t)(S + 16) * kM2Pitch * 4 + 15) & ~(size_t)15;
-  return regb + (size_t)nwaves * S * S * 8;
+  return regb + (size_t)nwaves * (S * S + 64) * 8;  // + each wave's selection scratch and spare entries
 }
 
 __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
@@ -571,7 +577,7 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
       wi[c] = (uint32_t)(wyy * SW + wxx);
     }
     uint64_t sel;
-    int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * SS, sel);
+    int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx2 + r * nmax;
     if (l == 0) {
@@ -659,7 +665,7 @@ constexpr int kM1pQuads = 16;
 constexpr int kM1pLoads = ((kMaxS + 9) * (kMaxS + 9) + kThreads - 1) / kThreads;
 __host__ __device__ inline size_t match1p_lds_bytes(int S) {
   const size_t chunk = (size_t)(S + 9) * (S + 9) * sizeof(f32x4);
-  const size_t sel = (size_t)(kThreads / 64) * S * S * 8;  // selection scratch, after the distances
+  const size_t sel = (size_t)(kThreads / 64) * (S * S + 64) * 8;  // selection scratch, after the distances
   return (chunk > sel ? chunk : sel) + 16 * 64 * 4;          // + the references' spectra
 }
 
@@ -670,7 +676,7 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
   const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6;
   const BlockGeom g = block_geom(h, w, d.nr, d.nc, S, 4, by, bx);
   const int SH = g.SH, SW = g.SW, SS = SH * SW;
-  const size_t chunk_bytes = (size_t)(S + 9) * (S + 9) * sizeof(f32x4), sel_bytes = (size_t)4 * S * S * 8;
+  const size_t chunk_bytes = (size_t)(S + 9) * (S + 9) * sizeof(f32x4), sel_bytes = (size_t)4 * (S * S + 64) * 8;
   f32x4* chunk = (f32x4*)smem;
   uint64_t* bufs = (uint64_t*)smem;
   float* refc = (float*)(smem + (chunk_bytes > sel_bytes ? chunk_bytes : sel_bytes));
@@ -769,7 +775,7 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
       wi[t] = (uint32_t)(wyy * SW + wxx);
     }
     uint64_t sel;
-    const int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * SS, sel);
+    const int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
     const size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx1 + r * nmax;
     if (l == 0) {
