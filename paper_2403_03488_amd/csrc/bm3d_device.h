@@ -427,8 +427,9 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
 // exceed theta survives: a candidate above it has nmax-1 others with
 // strictly smaller distances, so it cannot be among the n-1 smallest.  If
 // the bound does not exist, fewer than nmax-1 candidates pass: they are
-// counted and all survive.  Only the survivors are sorted on full 64-bit
-// keys.  buf holds at least as many entries as there are candidates, plus 64
+// counted and all survive.  Only the survivors are sorted, on full 64-bit
+// keys unless their 32-bit truncations already order them.  sel's low 10
+// bits are the window index.  buf holds at least as many entries as there are candidates, plus 64
 // spare entries from buf + spare.  Result as select_group.
 __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t (&wi)[16], int nmax,
                                        uint64_t* buf, int spare, uint64_t& sel) {
@@ -464,6 +465,26 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t 
     base += __popcll(b);
   }
   wave_lds_sync();
+  if (base <= 64) {
+    // One chunk: sort 32-bit keys (the distance's top 22 bits, the window
+    // index), which orders the survivors exactly unless two of them share
+    // their top 22 distance bits; then the full 64-bit keys are sorted.
+    const uint64_t v64 = l < base ? buf[l] : ~0ull;
+    const uint32_t hi = (uint32_t)(v64 >> 32);
+    uint32_t k32[1] = {l < base ? (hi & ~0x3FFu) | ((uint32_t)v64 & 0x3FFu) : ~0u};
+    wave_sort_n<uint32_t, 1>(k32);
+    const uint32_t next = (uint32_t)__shfl_down((int)k32[0], 1);
+    const bool tie = l < 63 && next != ~0u && k32[0] != ~0u && (k32[0] >> 10) == (next >> 10);
+    if (__ballot(tie) == 0) {
+      sel = k32[0] == ~0u ? ~0ull : (uint64_t)(k32[0] & 0x3FFu);
+    } else {
+      uint64_t v[1] = {v64};
+      wave_sort_n<uint64_t, 1>(v);
+      sel = v[0];
+    }
+    wave_lds_sync();
+    return n;
+  }
   uint64_t res[1] = {~0ull};
   for (int c0 = 0; c0 < base; c0 += 64) {
     uint64_t v[1] = {(c0 + l < base) ? buf[c0 + l] : ~0ull};

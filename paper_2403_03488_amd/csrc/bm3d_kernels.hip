@@ -504,6 +504,7 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
   if (b >= g.nci) return;
   const int wyy = l >> 1, wxx0 = (l & 1) * 16;
   const bool lane_ok = wyy < SH && wxx0 < SW;
+  const int wyy_c = lane_ok ? wyy : 0, wxx0_c = lane_ok ? wxx0 : 0;
   const float thr = d.thr2;
   const int rx = ref_pos(g.ci0 + b, w);
   int wx, t0;
@@ -530,14 +531,11 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
       float P[8], rw[23], rs[16];
 #pragma unroll
       for (int v = 0; v < 8; v++) P[v] = reg[(y - g.uy0) * kM2Pitch + rxr + v];
-      if (lane_ok) {
-        const float* src = reg + (y + dyo + wyy - g.uy0) * kM2Pitch + wxr + wxx0;
+      // a lane past the window reads the window's first row (its distances
+      // are never used), so no load is branched around
+      const float* src = reg + (y + dyo + wyy_c - g.uy0) * kM2Pitch + wxr + wxx0_c;
 #pragma unroll
-        for (int i = 0; i < 23; i++) rw[i] = src[i];
-      } else {
-#pragma unroll
-        for (int i = 0; i < 23; i++) rw[i] = 0.f;
-      }
+      for (int i = 0; i < 23; i++) rw[i] = src[i];
 #pragma unroll
       for (int c = 0; c < 16; c++) {
         float e = P[0] - rw[c];
@@ -1383,11 +1381,11 @@ __global__ void __launch_bounds__(kThreads) kb_prefilt(BatchRef br, KParams kp) 
   }
 }
 
-// The prefiltered matcher's LDS allows four workgroups per CU; its register
-// budget is held to match, so the compiler does not trade occupancy for
-// hoisted LDS reads.
+// The prefiltered matcher's LDS allows four workgroups per CU and the
+// step-2 matcher's three; their register budgets are held to match, so the
+// compiler does not trade occupancy for hoisted LDS reads.
 template <int STEP>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 4 : 1)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 4 : STEP == 2 ? 3 : 1)))
 kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
