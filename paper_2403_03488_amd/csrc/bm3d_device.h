@@ -419,7 +419,7 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
 }
 
 // Step-2 variant on FP32 distances.  db[t] = bit pattern of a non-negative
-// distance (~0u = not a candidate), wi[t] = its window index; the order is
+// distance (~0u = not a candidate), wi0 + wstep t its window index; the order is
 // (distance, window index) as 64-bit keys (bits << 32 | index).  The bound
 // theta is taken on the distances' top 16 bits (monotone in the distance,
 // 2^-7 relative): the (nmax-1)-th smallest among the lanes' two smallest
@@ -431,7 +431,7 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
 // keys unless their 32-bit truncations already order them.  sel's low 10
 // bits are the window index.  buf holds at least as many entries as there are candidates, plus 64
 // spare entries from buf + spare.  Result as select_group.
-__device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t (&wi)[16], int nmax,
+__device__ inline int select_group_f32(const uint32_t (&db)[16], int wi0, int wstep, int nmax,
                                        uint64_t* buf, int spare, uint64_t& sel) {
   const uint32_t NONE = ~0u;
   const int l = lane_id();
@@ -461,7 +461,7 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], const uint32_t 
   for (int t = 0; t < 16; t++) {
     const bool p = db[t] != NONE && (db[t] >> 16) <= th;
     const uint64_t b = __ballot(p);
-    buf[p ? base + __popcll(b & lt) : spare + l] = ((uint64_t)db[t] << 32) | wi[t];
+    buf[p ? base + __popcll(b & lt) : spare + l] = ((uint64_t)db[t] << 32) | (uint32_t)(wi0 + wstep * t);
     base += __popcll(b);
   }
   wave_lds_sync();

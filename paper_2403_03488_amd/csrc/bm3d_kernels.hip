@@ -505,6 +505,8 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
   const int wyy = l >> 1, wxx0 = (l & 1) * 16;
   const bool lane_ok = wyy < SH && wxx0 < SW;
   const int wyy_c = lane_ok ? wyy : 0, wxx0_c = lane_ok ? wxx0 : 0;
+  // this lane's columns c past the window (bit c set; all when the lane is)
+  const uint32_t colinv = !lane_ok ? 0xFFFFu : SW - wxx0 >= 16 ? 0u : (0xFFFFu << (SW - wxx0)) & 0xFFFFu;
   const float thr = d.thr2;
   const int rx = ref_pos(g.ci0 + b, w);
   int wx, t0;
@@ -565,17 +567,18 @@ __device__ void match2_block(const ImgDesc& d, const KParams& kp, int by, int bx
   for (int a = 0; a < 4; a++) {
     if (a >= na) break;
     const int ryr = ry[a] - g.uy0, wyr = wy[a] - g.uy0;
-    uint32_t db[16], wi[16];
+    // columns c of this lane that are no candidate of reference a: outside
+    // the window, or the reference itself (bit c set)
+    const int cself = wyr + wyy == ryr ? rxr - wxr - wxx0 : -1;
+    const uint32_t inv = colinv | ((unsigned)cself < 16u ? 1u << cself : 0u);
+    uint32_t db[16];
 #pragma unroll
     for (int c = 0; c < 16; c++) {
-      int wxx = wxx0 + c;
-      bool isref = (wyr + wyy == ryr) && (wxr + wxx == rxr);
-      bool ok = lane_ok && wxx < SW && !isref && acc[a][c] <= thr;
-      db[c] = ok ? __float_as_uint(acc[a][c]) : kNone32;
-      wi[c] = (uint32_t)(wyy * SW + wxx);
+      const uint32_t dbits = acc[a][c] <= thr ? __float_as_uint(acc[a][c]) : kNone32;
+      db[c] = dbits | (uint32_t)__builtin_amdgcn_sbfe((int)inv, c, 1);  // all ones where not a candidate
     }
     uint64_t sel;
-    int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
+    int n = select_group_f32(db, wyy * SW + wxx0, 1, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
     size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx2 + r * nmax;
     if (l == 0) {
@@ -763,17 +766,16 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 #pragma unroll
   for (int a = 0; a < 4; a++) {
     if (a >= na) break;
-    uint32_t db[16], wi[16];
+    uint32_t db[16];
 #pragma unroll
     for (int t = 0; t < 16; t++) {
       const int wxx = 2 * t + hx;
       const bool isref = (wy[a] + wyy == ry[a]) && (wx + wxx == rx);
       const bool ok = lane_ok && wxx < SW && !isref && acc[a][t] <= thr;
       db[t] = ok ? __float_as_uint(acc[a][t]) : kNone32;
-      wi[t] = (uint32_t)(wyy * SW + wxx);
     }
     uint64_t sel;
-    const int n = select_group_f32(db, wi, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
+    const int n = select_group_f32(db, wyy * SW + hx, 2, nmax, bufs + (size_t)wave * (S * S + 64), S * S, sel);
     const size_t r = (size_t)(g.ri0 + a) * d.nc + g.ci0 + b;
     int32_t* o = d.idx1 + r * nmax;
     if (l == 0) {
