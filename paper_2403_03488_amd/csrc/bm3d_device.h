@@ -306,21 +306,35 @@ __device__ inline void wave_lds_sync() {
 // least k values are <= the result).  Radix descent: bit by bit from the top,
 // a bit of the k-th smallest is 0 iff at least k values are <= the largest
 // number with the bits found so far and a 0 there.  NV vector compares per
-// bit; the counts and the prefix stay on the scalar unit.  Bits above hi
-// (wave-uniform) are taken as 0: the caller knows every value of interest
-// is below 2^(hi+1), and larger ones only raise the bound to all ones.
-template <int LO, int NV> __device__ inline uint32_t wave_kth_u32(const uint32_t (&v)[NV], int k, int hi = 31) {
+// bit; the counts and the prefix stay on the scalar unit.
+template <int LO, int NV> __device__ inline uint32_t wave_kth_u32(const uint32_t (&v)[NV], int k) {
   uint32_t prefix = 0;
-  if (hi < 31) {  // does the k-th smallest have a bit set above hi?
+#pragma unroll
+  for (int bit = 31; bit >= LO; bit--) {
+    const uint32_t t = prefix | ((1u << bit) - 1u);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NV; i++) c += __popcll(__ballot(v[i] <= t));
+    prefix = c < k ? prefix | (1u << bit) : prefix;
+  }
+  return prefix | ((1u << LO) - 1u);
+}
+// As wave_kth_u32, when every value of interest is known to lie below
+// 2^(hi+1) (hi wave-uniform, >= LO): the descent starts at bit hi (a rolled
+// loop on the scalar unit), and if fewer than k values lie below 2^(hi+1)
+// the bound is all ones.
+template <int LO, int NV> __device__ inline uint32_t wave_kth_u32_below(const uint32_t (&v)[NV], int k, int hi) {
+  if (hi >= 31) return wave_kth_u32<LO, NV>(v, k);
+  {
     const uint32_t t = (2u << hi) - 1u;
     int c = 0;
 #pragma unroll
     for (int i = 0; i < NV; i++) c += __popcll(__ballot(v[i] <= t));
     if (c < k) return ~0u;
   }
-#pragma unroll
-  for (int bit = 31; bit >= LO; bit--) {
-    if (bit > hi) continue;
+  uint32_t prefix = 0;
+#pragma unroll 1
+  for (int bit = hi; bit >= LO; bit--) {
     const uint32_t t = prefix | ((1u << bit) - 1u);
     int c = 0;
 #pragma unroll
@@ -374,7 +388,7 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
     uint32_t mn[1] = {k[r][0]};
 #pragma unroll
     for (int t = 1; t < 16; t++) mn[0] = kmin(mn[0], k[r][t]);
-    theta[r] = nmax > 1 ? wave_kth_u32<LO, 1>(mn, nmax - 1, hi) : (K)0;
+    theta[r] = nmax > 1 ? wave_kth_u32_below<LO, 1>(mn, nmax - 1, hi < LO ? LO : hi) : (K)0;
     n[r] = nmax;
     if (nmax > 1 && theta[r] == NONE) {  // fewer than nmax-1 lanes hold a candidate
       int npass = 0;

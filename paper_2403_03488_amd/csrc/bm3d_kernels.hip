@@ -400,6 +400,13 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
         keys[tid * RS + (ry - wy) * SW + (rx - wx)] = kNone32;  // above any threshold
       }
     }
+    // window positions past SS, up to the selection's last 64-entry row,
+    // read as non-candidates (so its loads need no per-lane test)
+    {
+      const int pad = ((SS + 63) & ~63) - SS;
+      for (int i = tid; i < kM1PassRefs * pad; i += blockDim.x)
+        keys[(i / pad) * RS + SS + i % pad] = kNone32;
+    }
     __syncthreads();
 
     // each wave selects the groups of local references wave + 4r + 8rd
@@ -421,7 +428,8 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
         for (int t = 0; t < 16; t++) {
           const int i = l + 64 * t;
-          const uint32_t dd = (act[r] && i < SS) ? keys[m * RS + i] : kNone32;
+          uint32_t dd = kNone32;
+          if (act[r] && 64 * t < SS) dd = keys[m * RS + i];  // wave-uniform test
           k[r][t] = dd <= thr ? ((dd << 10) | (uint32_t)i) : kNone32;
         }
       }
