@@ -828,15 +828,20 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 // the per-position sum of group weights, so the filter adds each member's
 // weight once, at its corner, into a global weight map (wsum); the
 // aggregation forms the denominator from it.
-// Four waves per workgroup and two or three workgroups per CU: while one
-// workgroup waits for its slowest wave or flushes, the others keep the SIMDs
-// busy.
-template <class XF> struct FilterCfg {
+// NGM is the largest group size in member tiles of 16 the kernel is built
+// for (1: n <= 16, as step 1 with its default size).  Without the 32-member
+// body a filter needs under 128 registers: workgroups of eight waves, two
+// per CU (four waves per SIMD).  With it, four waves per workgroup and two
+// or three workgroups per CU: step 1 in a 16-bit form fits 168 registers
+// per lane (3 waves per SIMD), the others need up to 256.  While one
+// workgroup waits for its slowest wave or flushes, the others keep the
+// SIMDs busy.
+template <class XF, int NGM = 2> struct FilterCfg {
   typedef typename XF::frag frag;
-  static constexpr int kWaves = 4;   // waves per workgroup
-  // workgroups per CU the registers allow: step 1 in a 16-bit form fits 168
-  // registers per lane (3 waves per SIMD), the others need up to 256
-  static constexpr int per_cu(int step) { return step == 1 && sizeof(frag) == 8 ? 3 : 2; }
+  static constexpr int kWaves = NGM == 1 ? 8 : 4;  // waves per workgroup
+  // workgroups per CU the registers allow
+  static constexpr int per_cu(int step) { return NGM == 1 ? 2 : step == 1 && sizeof(frag) == 8 ? 3 : 2; }
+  static constexpr int waves_per_simd(int step) { return per_cu(step) * kWaves / 4; }
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag); }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
   // region row pitch in 64-bit words: odd, so the rows of a member patch
@@ -854,9 +859,15 @@ template <class XF> struct FilterCfg {
 __host__ __device__ inline size_t filter_lds_bytes(int xform, int S, int T) {
   return xform == 0 ? FilterCfg<XF32>::bytes(S, T) : FilterCfg<XBF16>::bytes(S, T);
 }
-__host__ __device__ inline int filter_waves(int xform, int S, int T) {
-  return xform == 0 ? FilterCfg<XF32>::waves(S, T) : FilterCfg<XBF16>::waves(S, T);
+// waves per workgroup of a filter built for member-tile limit ngm (0: the
+// tile does not fit)
+__host__ __device__ inline int filter_waves(int xform, int S, int T, int ngm) {
+  const int w = ngm == 1 ? FilterCfg<XBF16, 1>::kWaves : FilterCfg<XBF16, 2>::kWaves;
+  return filter_lds_bytes(xform, S, T) <= kLdsBytes ? w : 0;
 }
+// the member-tile limit a filter launch is built for: one tile of 16 when no
+// group can be larger
+__host__ __device__ inline int filter_ngm(int nmax) { return nmax > 16 ? 2 : 1; }
 
 // Hadamard entry (+-1) of the n-point Sylvester matrix, 0 outside n x n.
 __device__ inline float had(int t, int g, int n) {
@@ -916,7 +927,7 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
 
 // One wave's part of a reference tile (geometry g): references drawn from
 // the workgroup's counter *lctr until the tile is exhausted.
-template <int STEP, class XF>
+template <int STEP, class XF, int NGM>
 __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const BlockGeom& g, int ch,
                                  const typename XF::frag* __restrict__ tabB,
                                  const typename XF::frag* __restrict__ tabA, int64_t* wreg, int* lctr) {
@@ -1208,7 +1219,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
     }
     };
-    if (n > 16) group(std::integral_constant<int, 2>());
+    if (NGM == 2 && n > 16) group(std::integral_constant<int, 2>());
     else group(std::integral_constant<int, 1>());
     have = have_next;
   }
@@ -1219,14 +1230,14 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
 // num, two rows per wave and iteration (pixels no member touched hold exact
 // zeros and are skipped), and cleared for the next tile together with the
 // reference counter.  The region and counter must be zero on entry.
-template <int STEP, class XF>
+template <int STEP, class XF, int NGM>
 __device__ void filter_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
                             const typename XF::frag* tabB, const typename XF::frag* tabA, int64_t* wreg,
                             int* lctr) {
   typedef FilterCfg<XF> C;
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const BlockGeom g = block_geom(d.h, d.w, d.nr, d.nc, S, kp.tile, ty, tx);
-  filter_tile_refs<STEP, XF>(d, kp, g, ch, tabB, tabA, wreg, lctr);
+  filter_tile_refs<STEP, XF, NGM>(d, kp, g, ch, tabB, tabA, wreg, lctr);
   __syncthreads();
   const int RH = g.ny + 7, RW = g.nx + 7, RP = C::pitch(RW);
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, l = lane_id();
@@ -1255,7 +1266,7 @@ __device__ inline void filter_lds_clear(int64_t* wreg, size_t region_bytes) {
 
 // One workgroup = as many waves as the LDS holds (blockDim.x / 64), each on
 // its own reference tile.
-template <int STEP, class XF>
+template <int STEP, class XF, int NGM>
 __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch, char* smem) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
@@ -1269,7 +1280,7 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   __syncthreads();
   const int ntx = (d.nc + kp.tile - 1) / kp.tile;
   const int t = blockIdx.x;
-  filter_tile<STEP, XF>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg, (int*)(wreg + rb / 8));
+  filter_tile<STEP, XF, NGM>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg, (int*)(wreg + rb / 8));
 }
 
 // image holding global item i: largest k with prefix[k] <= i
@@ -1282,7 +1293,7 @@ __device__ inline int find_img(const int* prefix, int n, int i) {
   return lo;
 }
 
-template <int STEP, class XF>
+template <int STEP, class XF, int NGM>
 __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
@@ -1316,7 +1327,7 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
-    filter_tile<STEP, XF>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl);
+    filter_tile<STEP, XF, NGM>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl);
     t += gridDim.x;
   }
   // every workgroup has drawn an index past the end; the last one to get
@@ -1347,11 +1358,11 @@ __global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   match2_block(d, kp, blockIdx.y, blockIdx.x, smem);
 }
-template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves)
-__attribute__((amdgpu_waves_per_eu(FilterCfg<XF>::per_cu(STEP)))) k_filter(ImgDesc d, KParams kp) {
+template <int STEP, class XF, int NGM>
+__global__ void __launch_bounds__((64 * FilterCfg<XF, NGM>::kWaves))
+__attribute__((amdgpu_waves_per_eu((FilterCfg<XF, NGM>::waves_per_simd(STEP))))) k_filter(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
-  filter_block_single<STEP, XF>(d, kp, blockIdx.y, smem);
+  filter_block_single<STEP, XF, NGM>(d, kp, blockIdx.y, smem);
 }
 
 // batched: each workgroup walks items begin + blockIdx.x, += gridDim.x
@@ -1409,11 +1420,11 @@ kb_match(BatchRef br, KParams kp) {
     __syncthreads();
   }
 }
-template <int STEP, class XF>
-__global__ void __launch_bounds__(64 * FilterCfg<XF>::kWaves)
-__attribute__((amdgpu_waves_per_eu(FilterCfg<XF>::per_cu(STEP)))) kb_filter(BatchRef br, KParams kp) {
+template <int STEP, class XF, int NGM>
+__global__ void __launch_bounds__((64 * FilterCfg<XF, NGM>::kWaves))
+__attribute__((amdgpu_waves_per_eu((FilterCfg<XF, NGM>::waves_per_simd(STEP))))) kb_filter(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
-  filter_block_batch<STEP, XF>(br, kp, smem);
+  filter_block_batch<STEP, XF, NGM>(br, kp, smem);
 }
 
 // ============================================================ launchers ==
@@ -1478,15 +1489,21 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
     case STAGE_FILTER1:
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
-      const int nw = filter_waves(xform, S, kp.tile);
+      const int ngm = filter_ngm(stage == STAGE_FILTER1 ? kp.n1 : kp.n2);
+      const int nw = filter_waves(xform, S, kp.tile, ngm);
       if (nw < 1) return -1;
       const int ntiles = ((d.nc + kp.tile - 1) / kp.tile) * ((d.nr + kp.tile - 1) / kp.tile);
       dim3 grid(ntiles, d.c);
       size_t b = filter_lds_bytes(xform, S, kp.tile);
 #define LAUNCH_F(STEP, XF)                                                                \
   do {                                                                                    \
-    lds_attr(k_filter<STEP, XF>, b);                                                      \
-    hipLaunchKernelGGL((k_filter<STEP, XF>), grid, dim3(64 * nw), b, s, d, kp);          \
+    if (ngm == 1) {                                                                       \
+      lds_attr(k_filter<STEP, XF, 1>, b);                                                 \
+      hipLaunchKernelGGL((k_filter<STEP, XF, 1>), grid, dim3(64 * nw), b, s, d, kp);     \
+    } else {                                                                              \
+      lds_attr(k_filter<STEP, XF, 2>, b);                                                 \
+      hipLaunchKernelGGL((k_filter<STEP, XF, 2>), grid, dim3(64 * nw), b, s, d, kp);     \
+    }                                                                                     \
   } while (0)
       if (stage == STAGE_FILTER1) {
         if (xform == 0) LAUNCH_F(1, XF32); else if (xform == 1) LAUNCH_F(1, XBF16); else LAUNCH_F(1, XF16);
@@ -1544,18 +1561,23 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
     case STAGE_FILTER1:
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
-      const int wv = filter_waves(xform, S, kp.tile);
+      const int ngm = filter_ngm(stage == STAGE_FILTER1 ? kp.n1 : kp.n2);
+      const int wv = filter_waves(xform, S, kp.tile, ngm);
       if (wv < 1) return -1;
       size_t b = filter_lds_bytes(xform, S, kp.tile);
       int g = blocks > 0 ? std::min(blocks, nw) : nw;
       // dynamic tiles: as many workgroups as fit on the device at once
-      if (br.ctr && cus > 0)
-        g = std::min(nw, cus * std::max(1, std::min(stage == STAGE_FILTER1 && xform != 0 ? 3 : 2,
-                                                    (int)(kLdsBytes / b))));
+      const int per_cu = ngm == 1 ? 2 : stage == STAGE_FILTER1 && xform != 0 ? 3 : 2;
+      if (br.ctr && cus > 0) g = std::min(nw, cus * std::max(1, std::min(per_cu, (int)(kLdsBytes / b))));
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
-    lds_attr(kb_filter<STEP, XF>, b);                                                     \
-    hipLaunchKernelGGL((kb_filter<STEP, XF>), dim3(g), dim3(64 * wv), b, s, br, kp);      \
+    if (ngm == 1) {                                                                       \
+      lds_attr(kb_filter<STEP, XF, 1>, b);                                                \
+      hipLaunchKernelGGL((kb_filter<STEP, XF, 1>), dim3(g), dim3(64 * wv), b, s, br, kp); \
+    } else {                                                                              \
+      lds_attr(kb_filter<STEP, XF, 2>, b);                                                \
+      hipLaunchKernelGGL((kb_filter<STEP, XF, 2>), dim3(g), dim3(64 * wv), b, s, br, kp); \
+    }                                                                                     \
   } while (0)
       if (stage == STAGE_FILTER1) {
         if (xform == 0) LAUNCH_FB(1, XF32); else if (xform == 1) LAUNCH_FB(1, XBF16); else LAUNCH_FB(1, XF16);
