@@ -348,9 +348,12 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     // this pass: reference columns v = CP*pass .. CP*pass + CP-1; local
     // reference index lr = CP*q + (v - CP*pass), key slot lr*RS + widx
     constexpr int CP = 4 / kM1Passes;
-    int slot[CP];
+    int slot[CP], spare[CP];
 #pragma unroll
-    for (int i = 0; i < CP; i++) slot[i] = (CP * q + i) * RS + wofs[CP * pass + i];
+    for (int i = 0; i < CP; i++) {
+      slot[i] = (CP * q + i) * RS + wofs[CP * pass + i];
+      spare[i] = (CP * q + i) * RS + S * S + col;
+    }
     // each wave takes whole candidate rows cy (every nwaves-th), all 16-column
     // blocks of a row at once (at most 3: the union window is <= 48 wide)
     for (int cy = wv; cy < g.ny; cy += nwaves) {
@@ -383,9 +386,11 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
 #pragma unroll
         for (int i = 0; i < CP; i++) {
           const int v = CP * pass + i;
-          // the distance alone; the key is formed when the slot is read back
-          if (in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW)
-            keys[slot[i] + t] = (uint32_t)(mnp[v] + nqc[j] - 2 * Dm[j][v]);
+          // the distance alone (the key is formed when the slot is read
+          // back); a candidate outside reference v's window goes to one of
+          // the reference's spare slots, so no store is branched around
+          const bool inw = in_rows && (unsigned)(cx - mwx[v]) < (unsigned)SW;
+          keys[inw ? slot[i] + t : spare[i]] = (uint32_t)(mnp[v] + nqc[j] - 2 * Dm[j][v]);
         }
       }
     }
