@@ -207,13 +207,15 @@ def tuned_params(args, bm3d, sigma, flags=0):
     if not args.no_autotune and not (args.tile and args.persistent >= 0):
         t0 = time.time()
         q = bm3d.autotune(p, None)
-        p.tile_refs, p.persistent_wgs = q.tile_refs, q.persistent_wgs
-        log("autotune: tile %d refs, persistent %d WG/CU (%.1fs)" % (p.tile_refs, p.persistent_wgs,
-                                                                     time.time() - t0))
+        p.tile_refs, p.persistent_wgs, p.match_refs = q.tile_refs, q.persistent_wgs, q.match_refs
+        log("autotune: tile %d refs, persistent %d WG/CU, step-1 matching %d refs per pass (%.1fs)" % (
+            p.tile_refs, p.persistent_wgs, p.match_refs, time.time() - t0))
     if args.tile:
         p.tile_refs = args.tile
     if args.persistent >= 0:
         p.persistent_wgs = args.persistent
+    if args.match_refs:
+        p.match_refs = args.match_refs
     return p
 
 
@@ -693,7 +695,7 @@ def measure_batch64(args, steps=None, warmup=None):
     plan.close()
     return {"MPps": mp / dt, "ms_per_step": dt * 1e3, "steps": steps, "megapixels": mp,
             "channel_megapixels": cmp, "channel_MPps": cmp / dt, "stages_ms": stage_ms,
-            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs,
+            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs, "match_refs": p.match_refs,
             "psnr_db": {"mean": float(np.mean(ps)), "min": float(np.min(ps))},
             "workload": "64 images, areas 128^2-1024^2, aspect 1:1-2:1, half grey / half colour, "
                         "sigma U[10,50], one graph-captured batched pass per step"}
@@ -718,7 +720,7 @@ def measure_highsigma(args, steps=None, warmup=None):
     res = {}
     for name, lam2d, xf in (("variant", 2.0, bm3d.T_BIOR15), ("default", 0.0, bm3d.T_DCT)):
         p = bm3d.params_default(sigma, xform=XF[args.xform])
-        p.tile_refs, p.persistent_wgs = base.tile_refs, base.persistent_wgs
+        p.tile_refs, p.persistent_wgs, p.match_refs = base.tile_refs, base.persistent_wgs, base.match_refs
         p.lambda_2d, p.transform_ht = lam2d, xf
         plan = bm3d.Batch(imgs, outs, [sigma] * B, p)
         stream = torch.cuda.Stream()
@@ -836,7 +838,7 @@ def measure_serving(args, n=None):
             "makespan_s": st["makespan_s"], "capacity_MPps": cap["MPps"], "requests": n, "mean_MP": mean_mp,
             "load": args.load, "rate_req_s": rate, "slots": args.slots, "ticks": loop.ticks,
             "mean_requests_per_tick": float(np.mean(loop.tick_sizes)), "peak_hbm_bytes": loop.peak_used,
-            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs,
+            "tile_refs": p.tile_refs, "persistent_wgs": p.persistent_wgs, "match_refs": p.match_refs,
             "fp32_single_image_path": {"MPps": base["MPps"], "p50_ms": base["p50_ms"],
                                        "p99_ms": base["p99_ms"], "makespan_s": base["makespan_s"]},
             "workload": "serving: %d requests, sides log-uniform 256-4096, 70%% grey / 30%% colour, "
@@ -875,6 +877,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="force the filter tile side (refs)")
     ap.add_argument("--persistent", type=int, default=-1, help="force workgroups per CU (0 = one per item)")
+    ap.add_argument("--match-refs", type=int, default=0, choices=(0, 8, 16),
+                    help="force the step-1 references per matching pass (0 = autotuned)")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed batched pass and stage timings (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -1044,7 +1048,7 @@ def main():
         "config": {"workload": "512x512 grey, sigma=25, S=32, N1=16, N2=32, stride 3, "
                                "batch of %d images per step, graph-captured batched pass" % B,
                    "batch": B, "xform": args.xform, "tile_refs": p.tile_refs,
-                   "persistent_wgs": p.persistent_wgs},
+                   "persistent_wgs": p.persistent_wgs, "match_refs": p.match_refs},
         "roofline": roof, "stages": per_stage, "pass_bound": pass_bound,
         "latency_ms_single_image": {"p50": float(np.percentile(lat_ms, 50)),
                                     "p99": float(np.percentile(lat_ms, 99))},

@@ -94,6 +94,10 @@ typedef struct {
                                 level (sigma grey, sigma/sqrt3 colour): the prefiltered
                                 matching of the high-noise profile (2.0 there) */
   int transform_ht;          /* step-1 2-D transform: BM3D_T_DCT or BM3D_T_BIOR15 */
+  int match_refs;            /* step-1 matching: references of a 4x4 block whose distances are
+                                held at once, 8 (two passes over the block's candidates) or
+                                16 (one pass); 0 = 16 where three blocks still fit a CU's LDS
+                                (S <= 25), else 8.  Results do not depend on it. */
 } bm3d_params;
 
 /* Step-1 2-D patch transforms.  Step 2 always uses the DCT. */
@@ -515,9 +519,10 @@ int bm3d_server_create(int max_requests, const bm3d_params* p, bm3d_server** ser
 int bm3d_server_tick(bm3d_server* server, const bm3d_request* reqs, int n, bm3d_stream_t stream);
 int bm3d_server_destroy(bm3d_server* server);
 
-/* Measures the candidate filter tile shapes / persistent grid sizes on the
- * current device for these params and writes the fastest into p
- * (tile_refs, persistent_wgs).  cache_path (optional) is a JSON file keyed by
+/* Measures the candidate filter tile shapes, persistent grid sizes and
+ * step-1 matching blocks (references per pass) on the current device for
+ * these params and writes the fastest into p (tile_refs, persistent_wgs,
+ * match_refs).  cache_path (optional) is a JSON file keyed by
  * device architecture, search size, max group size and transform form, read
  * before measuring and updated after.  Synchronises the device. */
 int bm3d_autotune(bm3d_params* p, const char* cache_path);

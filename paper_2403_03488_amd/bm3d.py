@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("persistent_wgs", ctypes.c_int), ("flags", ctypes.c_uint),
                 ("debug_nkept", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("lambda_2d", ctypes.c_float), ("transform_ht", ctypes.c_int)]
+                ("lambda_2d", ctypes.c_float), ("transform_ht", ctypes.c_int),
+                ("match_refs", ctypes.c_int)]
 
     def copy(self) -> "Params":
         q = Params()

@@ -29,6 +29,13 @@ constexpr float kMaxKaiserBeta = 50.f;
 
 int auto_tile(int S) { return S >= 24 ? 10 : 12; }
 
+// Step-1 references per matching pass when the params leave it open: one
+// pass over all 16 references of a block where three blocks still fit a CU's
+// LDS with its key buffer, two passes of 8 otherwise.
+int auto_match_refs(int S) {
+  return 3 * stage_lds_bytes(STAGE_MATCH1, 0, KParams{S, S, 1, 1, 1, 0, 16, {0}}) <= kLdsBudget ? 16 : 8;
+}
+
 // The filter tile (references per side of one workgroup's tile) must leave
 // every kernel within the LDS budget.
 bool tile_fits(const bm3d_params* p, int T) {
@@ -52,6 +59,7 @@ int check_params(const bm3d_params* p) {
   if (!(p->lambda_2d >= 0.f) || !isfinite(p->lambda_2d)) return BM3D_ERR_ARG;
   if (p->transform_ht != BM3D_T_DCT && p->transform_ht != BM3D_T_BIOR15) return BM3D_ERR_ARG;
   if (p->tile_refs < 0 || p->tile_refs > 16) return BM3D_ERR_ARG;
+  if (p->match_refs != 0 && p->match_refs != 8 && p->match_refs != 16) return BM3D_ERR_ARG;
   if (p->persistent_wgs < 0 || p->persistent_wgs > 64) return BM3D_ERR_ARG;
   if (p->tile_refs > 0 && !tile_fits(p, p->tile_refs)) return BM3D_ERR_UNSUPPORTED;
   return BM3D_OK;
@@ -155,6 +163,7 @@ KParams make_kparams(const bm3d_params* p) {
   k.n1 = p->n_ht;
   k.n2 = p->n_wie;
   k.tile = p->tile_refs > 0 ? p->tile_refs : auto_tile(std::max(p->search_ht, p->search_wie));
+  k.m1refs = p->match_refs > 0 ? p->match_refs : auto_match_refs(p->search_ht);
   double i0b = bessel_i0(p->kaiser_beta);
   for (int n = 0; n < 8; n++) {
     double r = 2.0 * n / 7.0 - 1.0;
@@ -789,8 +798,10 @@ std::string tune_key(const bm3d_params* p) {
   return k;
 }
 
-// Minimal reader/writer of a flat JSON object {"key": [tile, wgs, ms], ...}.
-bool cache_lookup(const char* path, const std::string& key, int* tile, int* wgs) {
+// Minimal reader/writer of a flat JSON object
+// {"key": [tile, wgs, match_refs, ms], ...}; entries of another form are
+// misses.
+bool cache_lookup(const char* path, const std::string& key, int* tile, int* wgs, int* mrefs) {
   if (!path) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
@@ -805,10 +816,10 @@ bool cache_lookup(const char* path, const std::string& key, int* tile, int* wgs)
   pos = s.find('[', pos);
   if (pos == std::string::npos) return false;
   float ms;
-  return sscanf(s.c_str() + pos, "[%d, %d, %f]", tile, wgs, &ms) == 3;
+  return sscanf(s.c_str() + pos, "[%d, %d, %d, %f]", tile, wgs, mrefs, &ms) == 4;
 }
 
-void cache_store(const char* path, const std::string& key, int tile, int wgs, float ms) {
+void cache_store(const char* path, const std::string& key, int tile, int wgs, int mrefs, float ms) {
   if (!path) return;
   std::string s;
   FILE* f = fopen(path, "r");
@@ -833,7 +844,7 @@ void cache_store(const char* path, const std::string& key, int tile, int wgs, fl
     }
   }
   char e[256];
-  snprintf(e, sizeof e, "\"%s\": [%d, %d, %.4f]", key.c_str(), tile, wgs, ms);
+  snprintf(e, sizeof e, "\"%s\": [%d, %d, %d, %.4f]", key.c_str(), tile, wgs, mrefs, ms);
   lines.push_back(e);
   f = fopen(path, "w");
   if (!f) return;
@@ -861,10 +872,11 @@ extern "C" int bm3d_autotune(bm3d_params* p, const char* cache_path) {
   int e = check_params(p);
   if (e) return e;
   const std::string key = tune_key(p);
-  int tile, wgs;
-  if (cache_lookup(cache_path, key, &tile, &wgs)) {
+  int tile, wgs, mrefs;
+  if (cache_lookup(cache_path, key, &tile, &wgs, &mrefs)) {
     p->tile_refs = tile;
     p->persistent_wgs = wgs;
+    p->match_refs = mrefs;
     return BM3D_OK;
   }
   // timing workload: 8 grey 512x512 images at sigma 25
@@ -886,14 +898,17 @@ extern "C" int bm3d_autotune(bm3d_params* p, const char* cache_path) {
   (void)hipEventCreate(&e1);
   const int tiles[] = {6, 8, 10, 12, 14, 16};
   const int grids[] = {0, 1, 2, 4};
+  const int mrs[] = {8, 16};
   float best = 1e30f;
-  int bt = auto_tile(std::max(p->search_ht, p->search_wie)), bg = 0;
+  int bt = auto_tile(std::max(p->search_ht, p->search_wie)), bg = 0, bm = auto_match_refs(p->search_ht);
   for (int t : tiles) {
     if (!tile_fits(p, t)) continue;
-    for (int gsz : grids) {
+    for (int gsz : grids)
+    for (int mr : mrs) {
       bm3d_params q = *p;
       q.tile_refs = t;
       q.persistent_wgs = gsz;
+      q.match_refs = mr;
       q.flags &= ~BM3D_FLAG_DEBUG_SYNC;
       bm3d_batch* b = nullptr;
       if (bm3d_batch_create(ds.data(), N, &q, &b) != BM3D_OK) continue;
@@ -912,6 +927,7 @@ extern "C" int bm3d_autotune(bm3d_params* p, const char* cache_path) {
         best = ms;
         bt = t;
         bg = gsz;
+        bm = mr;
       }
     }
   }
@@ -923,6 +939,7 @@ extern "C" int bm3d_autotune(bm3d_params* p, const char* cache_path) {
   if (best >= 1e29f) return BM3D_ERR_HIP;
   p->tile_refs = bt;
   p->persistent_wgs = bg;
-  cache_store(cache_path, key, bt, bg, best);
+  p->match_refs = bm;
+  cache_store(cache_path, key, bt, bg, bm, best);
   return BM3D_OK;
 }

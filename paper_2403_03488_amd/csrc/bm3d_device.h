@@ -75,6 +75,7 @@ struct KParams {
   int n1, n2;       // max group sizes
   int tile;         // filter tile side in references
   int prefilter;    // step-1 matching on thresholded 2-D spectra (lambda_2d > 0)
+  int m1refs;       // step-1 matching: references per pass over a block's candidates (8 or 16)
   float kaiser[8];  // 1-D Kaiser window
   // 8-point transforms of the 2-D patch transforms, in double so that the
   // 2-D products are rounded once: forward F[a][u] and inverse I[u][a] of

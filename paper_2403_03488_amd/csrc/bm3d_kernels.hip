@@ -207,20 +207,23 @@ __device__ inline BlockGeom block_geom(int h, int w, int nr, int nc, int S, int 
 // LDS: int8 luminance region [(S+16) rows][64 B used of kM1Pitch],
 // candidate norms [(S+9)][48] int32, keys of one pass [8 refs][S*S+72]
 // uint32 (also row-sum scratch; the last 64 slots of a reference are the
-// selection's spare entries).  The 16 references of a block are matched in two passes of 8
-// (reference columns 0-1, then 2-3), which halves the key buffer so that
-// three blocks fit a CU.
+// selection's spare entries).  The 16 references of a block are matched in
+// passes of PR references (PR = 8: reference columns 0-1, then 2-3; PR = 16:
+// all at once).  Two passes halve the key buffer, so that three blocks fit a
+// CU at S = 32; one pass forms each candidate's operands and cross terms
+// once instead of twice.
 // Row pitches are padded against LDS bank conflicts: region rows 80 B apart
 // (the four lane groups of a fragment read rows 2 apart, 40 dwords = 8 banks
 // mod 32), and per-reference key slots S*S+72 apart (lane groups store to
 // references 2 apart, 16 banks mod 32).
-constexpr int kM1Passes = 2, kM1PassRefs = 16 / kM1Passes, kM1Pitch = 80;
+constexpr int kM1Pitch = 80;
 __host__ __device__ inline int match1_key_stride(int S) { return S * S + 72; }
 // the selection's radix bound stops above this bit (distance bits below it:
 // 64 SSD units, a few more survivors at most)
 constexpr int kM1SelLo = 16;
-__host__ __device__ inline size_t match1_lds_bytes(int S) {
-  size_t keys = (size_t)kM1PassRefs * match1_key_stride(S) * 4, rs = (size_t)(S + 16) * 48 * 4;
+__host__ __device__ inline size_t match1_lds_bytes(int S, int pr) {
+  pr = pr == 16 ? 16 : 8;  // the launchers take every other value as 8
+  size_t keys = (size_t)pr * match1_key_stride(S) * 4, rs = (size_t)(S + 16) * 48 * 4;
   return (size_t)(S + 16) * kM1Pitch + (size_t)(S + 9) * 48 * 4 + (keys > rs ? keys : rs);
 }
 
@@ -236,7 +239,10 @@ __device__ inline uint64_t lds_bytes8(const uint8_t* base, int off) {
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
+template <int PR>
 __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx, char* smem) {
+  static_assert(PR == 8 || PR == 16, "two references per wave and selection round with four waves");
+  constexpr int kPasses = 16 / PR;
   const int S = kp.S1, nmax = kp.n1;
   const int h = d.h, w = d.w;
   const int tid = threadIdx.x, l = lane_id(), wave = tid >> 6, nwaves = blockDim.x >> 6;
@@ -344,10 +350,10 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
   const int wv = __builtin_amdgcn_readfirstlane(wave);
 
 #pragma unroll
-  for (int pass = 0; pass < kM1Passes; pass++) {
+  for (int pass = 0; pass < kPasses; pass++) {
     // this pass: reference columns v = CP*pass .. CP*pass + CP-1; local
     // reference index lr = CP*q + (v - CP*pass), key slot lr*RS + widx
-    constexpr int CP = 4 / kM1Passes;
+    constexpr int CP = 4 / kPasses;
     int slot[CP], spare[CP];
 #pragma unroll
     for (int i = 0; i < CP; i++) {
@@ -396,7 +402,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     }
     __syncthreads();
     // a reference is not its own candidate
-    if (tid < kM1PassRefs) {
+    if (tid < PR) {
       const int a = tid / CP, b = CP * pass + tid % CP;
       if (a < g.nri && b < g.nci) {
         int ry = ref_pos(g.ri0 + a, h), rx = ref_pos(g.ci0 + b, w), wy, wx, t0;
@@ -409,16 +415,15 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
     // read as non-candidates (so its loads need no per-lane test)
     {
       const int pad = ((SS + 63) & ~63) - SS;
-      for (int i = tid; i < kM1PassRefs * pad; i += blockDim.x)
+      for (int i = tid; i < PR * pad; i += blockDim.x)
         keys[(i / pad) * RS + SS + i % pad] = kNone32;
     }
     __syncthreads();
 
     // each wave selects the groups of local references wave + 4r + 8rd
     // (two at a time, side by side)
-    static_assert(kM1PassRefs % 8 == 0, "two references per wave and round with four waves");
 #pragma unroll 1
-    for (int rd = 0; rd < kM1PassRefs / 8; rd++) {
+    for (int rd = 0; rd < PR / 8; rd++) {
       uint32_t k[2][16];
       bool act[2];
       uint32_t* buf[2];
@@ -426,7 +431,7 @@ __device__ void match1_block(const ImgDesc& d, const KParams& kp, int by, int bx
       for (int r = 0; r < 2; r++) {
         const int m = wave + 4 * r + 8 * rd;
         const int a = m / CP, b = CP * pass + m % CP;
-        act[r] = m < kM1PassRefs && a < g.nri && b < g.nci;
+        act[r] = a < g.nri && b < g.nci;
         buf[r] = keys + (act[r] ? m : 0) * RS;
         // key = distance << 10 | window index for candidates within the
         // threshold (the distance is at most 2^22 - 1 there)
@@ -1355,9 +1360,9 @@ __global__ void __launch_bounds__(kThreads) k_agg2(ImgDesc d, KParams kp) {
   agg2_tile(d, kp, blockIdx.x, sh);
 }
 __global__ void __launch_bounds__(kThreads) k_lum(ImgDesc d) { lum_chunk(d, blockIdx.x); }
-__global__ void __launch_bounds__(kThreads) k_match1(ImgDesc d, KParams kp) {
+template <int PR> __global__ void __launch_bounds__(kThreads) k_match1(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
-  match1_block(d, kp, blockIdx.y, blockIdx.x, smem);
+  match1_block<PR>(d, kp, blockIdx.y, blockIdx.x, smem);
 }
 __global__ void __launch_bounds__(kThreads) k_match2(ImgDesc d, KParams kp) {
   extern __shared__ __align__(16) char smem[];
@@ -1410,7 +1415,8 @@ __global__ void __launch_bounds__(kThreads) kb_prefilt(BatchRef br, KParams kp) 
 // The prefiltered matcher's LDS allows four workgroups per CU and the
 // step-2 matcher's three; their register budgets are held to match, so the
 // compiler does not trade occupancy for hoisted LDS reads.
-template <int STEP>
+// PR: step-1 references per matching pass (unused by the other steps).
+template <int STEP, int PR = 8>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 4 : STEP == 2 ? 3 : 1)))
 kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
@@ -1419,7 +1425,7 @@ kb_match(BatchRef br, KParams kp) {
     const ImgDesc d = ldc(br.ds + im);  // by value: kept in registers
     const int j = i - br.prefix[im];
     const int nbx = (d.nc + 3) / 4;
-    if (STEP == 1) match1_block(d, kp, j / nbx, j % nbx, smem);
+    if (STEP == 1) match1_block<PR>(d, kp, j / nbx, j % nbx, smem);
     else if (STEP == 3) match1p_block(d, kp, j / nbx, j % nbx, smem);  // prefiltered step 1
     else match2_block(d, kp, j / nbx, j % nbx, smem);
     __syncthreads();
@@ -1481,9 +1487,14 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
     case STAGE_MATCH2: {
       dim3 grid((d.nc + 3) / 4, (d.nr + 3) / 4);
       if (stage == STAGE_MATCH1) {
-        size_t b = match1_lds_bytes(kp.S1);
-        lds_attr(k_match1, b);
-        hipLaunchKernelGGL(k_match1, grid, dim3(kThreads), b, s, d, kp);
+        size_t b = match1_lds_bytes(kp.S1, kp.m1refs);
+        if (kp.m1refs == 16) {
+          lds_attr(k_match1<16>, b);
+          hipLaunchKernelGGL(k_match1<16>, grid, dim3(kThreads), b, s, d, kp);
+        } else {
+          lds_attr(k_match1<8>, b);
+          hipLaunchKernelGGL(k_match1<8>, grid, dim3(kThreads), b, s, d, kp);
+        }
       } else {
         size_t b = match2_lds_bytes(kp.S2, kThreads / 64);
         lds_attr(k_match2, b);
@@ -1540,9 +1551,14 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
       hipLaunchKernelGGL(kb_elem, dim3(grid), dim3(kThreads), 0, s, stage, br, kp);
       break;
     case STAGE_MATCH1: {
-      size_t b = match1_lds_bytes(kp.S1);
-      lds_attr(kb_match<1>, b);
-      hipLaunchKernelGGL(kb_match<1>, dim3(grid), dim3(kThreads), b, s, br, kp);
+      size_t b = match1_lds_bytes(kp.S1, kp.m1refs);
+      if (kp.m1refs == 16) {
+        lds_attr(kb_match<1, 16>, b);
+        hipLaunchKernelGGL((kb_match<1, 16>), dim3(grid), dim3(kThreads), b, s, br, kp);
+      } else {
+        lds_attr(kb_match<1, 8>, b);
+        hipLaunchKernelGGL((kb_match<1, 8>), dim3(grid), dim3(kThreads), b, s, br, kp);
+      }
       break;
     }
     case STAGE_PREFILT: {
@@ -1600,7 +1616,7 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
 
 size_t stage_lds_bytes(int stage, int xform, const KParams& kp) {
   switch (stage) {
-    case STAGE_MATCH1: return match1_lds_bytes(kp.S1);
+    case STAGE_MATCH1: return match1_lds_bytes(kp.S1, kp.m1refs);
     case STAGE_PREFILT: return prefilt_lds_bytes();
     case STAGE_MATCH1P: return match1p_lds_bytes(kp.S1);
     case STAGE_MATCH2: return match2_lds_bytes(kp.S2, kThreads / 64);

@@ -42,8 +42,9 @@ def test_every_declared_symbol_is_exported(B):
 
 
 def test_struct_layout_matches_header(B):
-    # bm3d_params: 4 ints, 4 floats, 4 ints/unsigned, 2 pointers, size_t, float, int
-    assert ctypes.sizeof(B.Params) == 4 * 4 + 4 * 4 + 4 * 4 + 8 + 8 + 8 + 4 + 4
+    # bm3d_params: 4 ints, 4 floats, 4 ints/unsigned, 2 pointers, size_t, float, 2 ints
+    # (padded to the pointers' 8-byte alignment)
+    assert ctypes.sizeof(B.Params) == 4 * 4 + 4 * 4 + 4 * 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4
     assert ctypes.sizeof(B.ImageDesc) == 8 + 8 + 3 * 4 + 4
 
 
@@ -226,7 +227,8 @@ def test_host_validation_rejects_before_enqueue(B):
     for field, val in (("n_wie", 24), ("n_ht", 0), ("search_ht", 33), ("search_wie", 0),
                        ("lambda_ht", -1.0), ("tau_wie", float("nan")), ("xform", 7),
                        ("kaiser_beta", float("inf")), ("tile_refs", 17), ("lambda_2d", -1.0),
-                       ("lambda_2d", float("nan")), ("transform_ht", 2)):
+                       ("lambda_2d", float("nan")), ("transform_ht", 2), ("match_refs", 4),
+                       ("match_refs", -8), ("match_refs", 32)):
         q = p.copy()
         setattr(q, field, val)
         assert L.bm3d_denoise(fake, 64, 64, 1, 25.0, ref(q), fake, None) == -1, field

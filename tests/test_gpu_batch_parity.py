@@ -68,9 +68,9 @@ def bench16():
     return [synth.gray_512(index=i, sigma=25.0) for i in range(16)]
 
 
-def make_plan(B, samples, xform, tile=TILE, persistent=0, flags=0):
+def make_plan(B, samples, xform, tile=TILE, persistent=0, flags=0, match_refs=0):
     p = B.params_default(25.0, xform=xform, flags=flags | B.FLAG_SIGMA_PROFILE)
-    p.tile_refs, p.persistent_wgs = tile, persistent
+    p.tile_refs, p.persistent_wgs, p.match_refs = tile, persistent, match_refs
     imgs = [dev(s.noisy) for s in samples]
     outs = [torch.empty(s.noisy.shape, dtype=torch.float32, device="cuda") for s in samples]
     return B.Batch(imgs, outs, [s.sigma for s in samples], p), imgs, outs, p
@@ -112,12 +112,12 @@ def test_mixed_batch_step1_bit_exact(B):
     plan.close()
 
 
-@pytest.mark.parametrize("tile", [8, 10])
-def test_bench_config_step1_bit_exact(B, tile):
+@pytest.mark.parametrize("tile,match_refs", [(8, 0), (10, 0), (10, 16)])
+def test_bench_config_step1_bit_exact(B, tile, match_refs):
     samples = bench16()
-    plan, *_ = make_plan(B, samples, xform=1, tile=tile)
+    plan, *_ = make_plan(B, samples, xform=1, tile=tile, match_refs=match_refs)
     replay_graph(plan)
-    check_step1_bit_exact(B, plan, samples, "16 x 512^2 tile %d" % tile)
+    check_step1_bit_exact(B, plan, samples, "16 x 512^2 tile %d refs/pass %d" % (tile, match_refs))
     plan.close()
 
 

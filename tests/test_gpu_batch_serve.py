@@ -247,10 +247,11 @@ def test_autotune_cache_roundtrip(B, tmp_path):
     path = str(tmp_path / "tune.json")
     p = B.params_default(25.0, xform=1)
     q = B.autotune(p, path)
-    assert q.tile_refs >= 2 and q.persistent_wgs >= 0
+    assert q.tile_refs >= 2 and q.persistent_wgs >= 0 and q.match_refs in (8, 16)
     data = json.load(open(path))
     assert len(data) == 1
-    key, (tile, wgs, ms) = next(iter(data.items()))
-    assert "gfx" in key and tile == q.tile_refs and wgs == q.persistent_wgs and ms > 0
+    key, (tile, wgs, mrefs, ms) = next(iter(data.items()))
+    assert "gfx" in key and tile == q.tile_refs and wgs == q.persistent_wgs and mrefs == q.match_refs
+    assert ms > 0
     r = B.autotune(p, path)  # served from the cache
-    assert (r.tile_refs, r.persistent_wgs) == (q.tile_refs, q.persistent_wgs)
+    assert (r.tile_refs, r.persistent_wgs, r.match_refs) == (q.tile_refs, q.persistent_wgs, q.match_refs)

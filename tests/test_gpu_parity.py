@@ -123,10 +123,22 @@ def match1_cases():
 
 @pytest.mark.parametrize("case", list(match1_cases()), ids=lambda c: c[0])
 def test_match1_bit_exact(B, case):
+    run_match1(B, case)
+
+
+# Both matching blocks (references per pass over a block's candidates) at
+# both search sizes: the groups do not depend on the block.
+@pytest.mark.parametrize("match_refs", [8, 16])
+@pytest.mark.parametrize("name", ["small_gray", "gray512_s50", "ragged_37x53", "thin_9x100", "low_entropy"])
+def test_match1_blocks_bit_exact(B, name, match_refs):
+    run_match1(B, next(c for c in match1_cases() if c[0] == name), match_refs)
+
+
+def run_match1(B, case, match_refs=0):
     name, lum, S, tau, nmax = case
-    log("match1 %s %s S=%d tau=%s n=%d" % (name, lum.shape, S, tau, nmax))
+    log("match1 %s %s S=%d tau=%s n=%d refs/pass=%d" % (name, lum.shape, S, tau, nmax, match_refs))
     h, w = lum.shape
-    p = gparams(B, 25.0, S, n_ht=nmax, tau_ht=tau)
+    p = gparams(B, 25.0, S, n_ht=nmax, tau_ht=tau, match_refs=match_refs)
     R = B.num_refs(h, w)
     idx = torch.full((R, nmax), -7, dtype=torch.int32, device="cuda")
     cnt = torch.zeros(R, dtype=torch.int32, device="cuda")
