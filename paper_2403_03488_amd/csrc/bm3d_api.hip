@@ -39,9 +39,9 @@ int auto_match_refs(int S) {
 // The filter tile (references per side of one workgroup's tile) must leave
 // every kernel within the LDS budget.
 bool tile_fits(const bm3d_params* p, int T) {
-  for (int S : {p->search_ht, p->search_wie})
-    if (stage_lds_bytes(STAGE_FILTER1, p->xform, KParams{S, S, 1, 1, T, {0}}) > kLdsBudget) return false;
-  return true;
+  const KParams k{p->search_ht, p->search_wie, 1, 1, T, 0, 8, {0}};
+  return stage_lds_bytes(STAGE_FILTER1, p->xform, k) <= kLdsBudget &&
+         stage_lds_bytes(STAGE_FILTER2, p->xform, k) <= kLdsBudget;
 }
 
 int check_params(const bm3d_params* p) {
@@ -58,7 +58,7 @@ int check_params(const bm3d_params* p) {
   if (p->xform < BM3D_XF_FP32 || p->xform > BM3D_XF_FP16) return BM3D_ERR_ARG;
   if (!(p->lambda_2d >= 0.f) || !isfinite(p->lambda_2d)) return BM3D_ERR_ARG;
   if (p->transform_ht != BM3D_T_DCT && p->transform_ht != BM3D_T_BIOR15) return BM3D_ERR_ARG;
-  if (p->tile_refs < 0 || p->tile_refs > 16) return BM3D_ERR_ARG;
+  if (p->tile_refs < 0 || p->tile_refs > kMaxTile) return BM3D_ERR_ARG;
   if (p->match_refs != 0 && p->match_refs != 8 && p->match_refs != 16) return BM3D_ERR_ARG;
   if (p->persistent_wgs < 0 || p->persistent_wgs > 64) return BM3D_ERR_ARG;
   if (p->tile_refs > 0 && !tile_fits(p, p->tile_refs)) return BM3D_ERR_UNSUPPORTED;

@@ -10,6 +10,7 @@ namespace bm3d {
 constexpr int kP = 8;       // patch side
 constexpr int kStride = 3;  // reference stride
 constexpr int kMaxS = 32;   // largest search window side (10-bit window index)
+constexpr int kMaxTile = 16; // largest filter tile side (references)
 constexpr int kWave = 64;
 
 // ------------------------------------------------------------ geometry ---
@@ -549,6 +550,13 @@ struct XBF16 {
   static constexpr bool kScaledInverse = true;
   typedef bf16x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
+  // two values rounded as cvt rounds them, a in the low half
+  static __device__ inline uint32_t pack2(float a, float b) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+  }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
   }
@@ -564,6 +572,12 @@ struct XF16 {
   static constexpr bool kScaledInverse = false;
   typedef f16x4 frag;
   static __device__ inline frag cvt(f32x4 a) { return __builtin_convertvector(a, frag); }
+  static __device__ inline uint32_t pack2(float a, float b) {
+    typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+  }
   static __device__ inline f32x4 mma(frag a, frag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
   }

@@ -860,20 +860,27 @@ template <class XF, int NGM = 2> struct FilterCfg {
   static __host__ __device__ size_t region(int S, int T) {
     return (size_t)rnum(S, T) * pitch(rnum(S, T)) * sizeof(int64_t);
   }
-  // tables, region, then the reference counter and the tile index
-  static __host__ __device__ size_t bytes(int S, int T) { return tables() + region(S, T) + 16; }
-  // waves per workgroup (0: the tile does not fit)
-  static __host__ __device__ int waves(int S, int T) { return bytes(S, T) <= kLdsBytes ? kWaves : 0; }
+  // bytes per position of the staged pixels: one dword with 16-bit operands
+  // and in FP32 step 1, a float pair in FP32 step 2
+  static __host__ __device__ int pix_elem(int step) { return sizeof(frag) == 8 || step == 1 ? 4 : 8; }
+  static __host__ __device__ size_t pixels(int step, int S, int T) {
+    return (size_t)rnum(S, T) * pitch(rnum(S, T)) * pix_elem(step);
+  }
+  // tables, region, the reference counter and the tile index, then the
+  // staged pixels
+  static __host__ __device__ size_t bytes(int step, int S, int T) {
+    return tables() + region(S, T) + 16 + pixels(step, S, T);
+  }
 };
 
-__host__ __device__ inline size_t filter_lds_bytes(int xform, int S, int T) {
-  return xform == 0 ? FilterCfg<XF32>::bytes(S, T) : FilterCfg<XBF16>::bytes(S, T);
+__host__ __device__ inline size_t filter_lds_bytes(int xform, int step, int S, int T) {
+  return xform == 0 ? FilterCfg<XF32>::bytes(step, S, T) : FilterCfg<XBF16>::bytes(step, S, T);
 }
 // waves per workgroup of a filter built for member-tile limit ngm (0: the
 // tile does not fit)
-__host__ __device__ inline int filter_waves(int xform, int S, int T, int ngm) {
+__host__ __device__ inline int filter_waves(int xform, int step, int S, int T, int ngm) {
   const int w = ngm == 1 ? FilterCfg<XBF16, 1>::kWaves : FilterCfg<XBF16, 2>::kWaves;
-  return filter_lds_bytes(xform, S, T) <= kLdsBytes ? w : 0;
+  return filter_lds_bytes(xform, step, S, T) <= kLdsBytes ? w : 0;
 }
 // the member-tile limit a filter launch is built for: one tile of 16 when no
 // group can be larger
@@ -935,12 +942,96 @@ __device__ void filter_tables(typename XF::frag* tabB, typename XF::frag* tabA, 
   }
 }
 
+// Stages a tile's pixels in LDS: rows uy0 .. uy0+ny+6 and columns
+// ux0 .. ux0+nx+6 of channel ch (every member patch of the tile lies there),
+// minus the channel centre, in the operand form of the forward transform, at
+// row pitch PP positions.  With 16-bit operands a position is one dword: in
+// step 1 the values at x and x+1 (so that any 4-pixel run is two dwords), in
+// step 2 the noisy and the basic value at x.  With FP32 operands it is the
+// noisy value (step 1) or the (noisy, basic) pair (step 2).  Each value is
+// rounded as the transform's operand conversion rounds it.  NT threads; a
+// thread issues its loads in batches of kB positions before using them.
+template <int STEP, class XF, int NT>
+__device__ void filter_stage_pixels(const ImgDesc& d, const BlockGeom& g, int ch, int PP, void* pix) {
+  constexpr int kSide = 3 * (kMaxTile - 1) + kMaxS + 7;  // largest region side
+  constexpr int kB = 8;
+  const int RW = g.nx + 7, npos = (g.ny + 7) * RW;
+  // position i is (i / RW, i % RW); (i * M) >> 20 is the quotient for every
+  // i below 2^13 and RW <= kSide
+  static_assert(kSide * kSide <= (1 << 13), "quotient range");
+  const uint32_t M = (1u << 20) / (uint32_t)RW + 1u;
+  const size_t hw = (size_t)d.h * d.w;
+  const float* __restrict__ noisy = d.planar + ch * hw;
+  const float* __restrict__ second = STEP == 1 ? noisy : d.basic + ch * hw;
+  const float c = channel_centre(d.c, ch);
+  for (int i0 = threadIdx.x; i0 < npos; i0 += kB * NT) {
+    float va[kB], vb[kB];
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      const int i = i0 + k * NT;
+      const int ii = i < npos ? i : 0;  // past the region: a valid stand-in
+      const int y = (int)(((uint32_t)ii * M) >> 20), x = ii - y * RW;
+      const size_t o = (size_t)(g.uy0 + y) * d.w + g.ux0 + x;
+      va[k] = ldg(noisy + o);
+      // step 1: the value at x+1 (the region's last column has none: never read)
+      vb[k] = ldg(second + o + (STEP == 1 && x + 1 < RW ? 1 : 0));
+    }
+#pragma unroll
+    for (int k = 0; k < kB; k++) {
+      const int i = i0 + k * NT;
+      if (i >= npos) break;
+      const int y = (int)(((uint32_t)i * M) >> 20), x = i - y * RW;
+      const float a = va[k] - c, b = vb[k] - c;
+      if constexpr (sizeof(typename XF::frag) == 8) {
+        ((uint32_t*)pix)[y * PP + x] = XF::pack2(a, b);
+      } else if (STEP == 1) {
+        ((float*)pix)[y * PP + x] = a;
+      } else {
+        ((float2*)pix)[y * PP + x] = make_float2(a, b);
+      }
+    }
+  }
+}
+
+// The A-operand fragment of 4 adjacent staged pixels from position e: the
+// noisy values into fa and, in step 2, the basic ones into fb.
+template <int STEP, class XF>
+__device__ inline void pixel_frags(const void* pix, int e, typename XF::frag& fa, typename XF::frag& fb) {
+  typedef typename XF::frag frag;
+  if constexpr (sizeof(frag) == 8) {
+    const uint32_t* P = (const uint32_t*)pix + e;
+    if (STEP == 1) {
+      const uint2 u = {P[0], P[2]};
+      fa = __builtin_bit_cast(frag, u);
+    } else {
+      const uint32_t p0 = P[0], p1 = P[1], p2 = P[2], p3 = P[3];
+      // byte permutes: low halves of (p0, p1) for the noisy values, high
+      // halves for the basic ones (selector bytes 0-3 index p0, 4-7 p1)
+      const uint2 n = {__builtin_amdgcn_perm(p1, p0, 0x05040100u), __builtin_amdgcn_perm(p3, p2, 0x05040100u)};
+      const uint2 b = {__builtin_amdgcn_perm(p1, p0, 0x07060302u), __builtin_amdgcn_perm(p3, p2, 0x07060302u)};
+      fa = __builtin_bit_cast(frag, n);
+      fb = __builtin_bit_cast(frag, b);
+    }
+  } else if (STEP == 1) {
+    const float* P = (const float*)pix + e;
+    f32x4 a = {P[0], P[1], P[2], P[3]};
+    fa = a;
+  } else {
+    const float2* P = (const float2*)pix + e;
+    const float2 p0 = P[0], p1 = P[1], p2 = P[2], p3 = P[3];
+    f32x4 a = {p0.x, p1.x, p2.x, p3.x}, b = {p0.y, p1.y, p2.y, p3.y};
+    fa = a;
+    fb = b;
+  }
+}
+
 // One wave's part of a reference tile (geometry g): references drawn from
 // the workgroup's counter *lctr until the tile is exhausted.
 template <int STEP, class XF, int NGM>
 __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const BlockGeom& g, int ch,
                                  const typename XF::frag* __restrict__ tabB,
-                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg, int* lctr) {
+                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg, int* lctr,
+                                 const void* __restrict__ pix) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
   const int nmax = STEP == 1 ? kp.n1 : kp.n2;
@@ -954,8 +1045,6 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
   int64_t* __restrict__ gwsum = d.wsum + ch * hw;
 
   const float centre = channel_centre(d.c, ch);
-  const float* __restrict__ noisy = d.planar + ch * hw;
-  const float* __restrict__ basic = d.basic + ch * hw;
   const float sig2 = d.sigma * d.sigma;
   const float thr = d.lam_sigma;
   const float inv_w = 1.f / (float)w;
@@ -963,10 +1052,10 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
   int hn = 0;
   const int nrefs = g.nri * g.nci;
   // A reference's group size and member slots are loaded two references
-  // ahead; its member positions and noisy member pixels are formed and
-  // loaded while the previous reference is inverted and aggregated (slots
-  // beyond the group hold -1 and are ignored below).  Step 2 issues the
-  // loads of its basic pixels before the noisy transform, which hides them.
+  // ahead; its member positions are formed while the previous reference is
+  // inverted and aggregated (slots beyond the group hold -1 and are ignored
+  // below), and its members' operand fragments are read from the tile's
+  // staged pixels.
   // References come from the workgroup's counter (row-major within the
   // tile), one draw per reference, two ahead of their use.
   auto draw = [&]() {
@@ -986,9 +1075,23 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
     for (int gt = 0; gt < 2; gt++) gi_nx[gt] = ldg(idx + rn * nmax + (16 * gt + col < nmax ? 16 * gt + col : 0));
   };
   int n_nx = 1, my_nx[2], mx_nx[2];
+  // Operand fragments of a reference's members from the staged pixels:
+  // member rows 2kt + q/2, columns 4(q&1) .. +3; noisy into fa, basic into
+  // fb (step 2).  With 16-bit operands they are read one reference ahead,
+  // with FP32 operands (twice the registers) when the group starts.
+  constexpr bool kEarlyFrags = sizeof(frag) == 8;
+  frag fa[2][4], fb[2][4];
+  auto read_frags = [&](int n, const int (&my)[2], const int (&mx)[2]) {
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      if (gt == 1 && n <= 16) break;
+      const int e0 = (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
+#pragma unroll
+      for (int kt = 0; kt < 4; kt++) pixel_frags<STEP, XF>(pix, e0 + 2 * kt * RP, fa[gt][kt], fb[gt][kt]);
+    }
+  };
   bool mv_nx[2];
   size_t r_st = 0;  // global index of the staged reference
-  f32x4 an[2][4];  // noisy member pixels of the next reference
   auto stage = [&]() {
     r_st = r_nx;
     // group size and everything derived from it are wave-uniform
@@ -1008,16 +1111,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
       my_nx[gt] = inside ? yy : g.uy0;
       mx_nx[gt] = inside ? xx : g.ux0;
     }
-#pragma unroll
-    for (int gt = 0; gt < 2; gt++) {
-      if (gt == 1 && n_nx <= 16) break;
-#pragma unroll
-      for (int kt = 0; kt < 4; kt++) {
-        const float* src = noisy + (size_t)(my_nx[gt] + 2 * kt + (q >> 1)) * w + mx_nx[gt] + 4 * (q & 1);
-#pragma unroll
-        for (int v = 0; v < 4; v++) an[gt][kt][v] = ldg(src + v);  // always a valid pixel
-      }
-    }
+    if (kEarlyFrags) read_frags(n_nx, my_nx, mx_nx);
   };
   bool have = k_pf < nrefs;
   if (have) {
@@ -1056,19 +1150,16 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
     constexpr int NG = decltype(ng_c)::value;
     // ---- forward: 2-D DCT then WHT of the noisy (and in step 2 the basic) group
     f32x4 D2[2][4], D2b[2][4];
-    f32x4 ab[2][4];  // step 2: basic member pixels, in flight during the noisy transform
-    if (STEP == 2) {
+    if (!kEarlyFrags) read_frags(n, my, mx);
+    // an absent member enters as a zero patch
 #pragma unroll
-      for (int gt = 0; gt < 2; gt++) {
-        if (gt >= NG) break;
+    for (int gt = 0; gt < 2; gt++) {
+      if (gt >= NG) break;
+      if (!all_present && !mv[gt]) {
+        const frag z = XF::cvt(zero4());
 #pragma unroll
-        for (int kt = 0; kt < 4; kt++) {
-          const float* src = basic + (size_t)(my[gt] + 2 * kt + (q >> 1)) * w + mx[gt] + 4 * (q & 1);
-#pragma unroll
-          for (int v = 0; v < 4; v++) ab[gt][kt][v] = ldg(src + v);  // always a valid pixel
-        }
+        for (int kt = 0; kt < 4; kt++) fa[gt][kt] = fb[gt][kt] = z;
       }
-      __builtin_amdgcn_sched_barrier(0);  // the loads are issued before the noisy transform
     }
 #pragma unroll
     for (int src_i = 0; src_i < (STEP == 2 ? 2 : 1); src_i++) {
@@ -1076,20 +1167,12 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
-        f32x4 a[4];
-#pragma unroll
-        for (int kt = 0; kt < 4; kt++) a[kt] = src_i == 0 ? an[gt][kt] : ab[gt][kt];
-        if (!all_present) {  // an absent member enters as a zero patch
-#pragma unroll
-          for (int kt = 0; kt < 4; kt++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) a[kt][v] = mv[gt] ? a[kt][v] : centre;
-        }
 #pragma unroll
         for (int nt = 0; nt < 4; nt++) D1[gt][nt] = zero4();
 #pragma unroll
         for (int k2 = 0; k2 < 2; k2++) {
-          const frag a0 = XF::cvt(a[2 * k2] - centre), a1 = XF::cvt(a[2 * k2 + 1] - centre);
+          const frag a0 = src_i == 0 ? fa[gt][2 * k2] : fb[gt][2 * k2];
+          const frag a1 = src_i == 0 ? fa[gt][2 * k2 + 1] : fb[gt][2 * k2 + 1];
 #pragma unroll
           for (int nt = 0; nt < 4; nt++) {
             const frag* tb = tabB + ((k2 * 4 + nt) * 64 + l) * 2;
@@ -1207,25 +1290,34 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
     // (q, col) holds pixels (2 mt + q/2, 4 (q&1) + v) of member 16 gt + col:
     // one base address per lane, the rest immediate offsets.  An absent
     // member has weight 0 and a valid (corner) position.
+    frag b3[2][4];
+    int64_t* rb[2];
 #pragma unroll
     for (int gt = 0; gt < 2; gt++) {
       if (gt >= NG) break;
-      frag b3[4];
 #pragma unroll
-      for (int ct = 0; ct < 4; ct++) b3[ct] = XF::cvt(D3[ct][gt]);
-      int64_t* rb = wreg + (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
+      for (int ct = 0; ct < 4; ct++) b3[gt][ct] = XF::cvt(D3[ct][gt]);
+      rb[gt] = wreg + (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
+    }
+    // each table fragment is read once for both member tiles
 #pragma unroll
-      for (int mt = 0; mt < 4; mt++) {
-        f32x4 acc = zero4();
+    for (int mt = 0; mt < 4; mt++) {
+      const frag* ta0 = tabA + ((mt * 2) * 64 + l) * 2;
+      const frag* ta1 = tabA + ((mt * 2 + 1) * 64 + l) * 2;
+      const frag t00 = ta0[0], t01 = ta0[1], t10 = ta1[0], t11 = ta1[1];
 #pragma unroll
-        for (int c2 = 0; c2 < 2; c2++) {
-          const frag* ta = tabA + ((mt * 2 + c2) * 64 + l) * 2;
-          acc = XF::mma2(ta[0], ta[1], b3[2 * c2], b3[2 * c2 + 1], acc);
-        }
-        int64_t* rr = rb + 2 * mt * RP;
+      for (int gt = 0; gt < 2; gt++) {
+        if (gt >= NG) break;
+        f32x4 acc = XF::mma2(t00, t01, b3[gt][0], b3[gt][1], zero4());
+        acc = XF::mma2(t10, t11, b3[gt][2], b3[gt][3], acc);
+        int64_t* rr = rb[gt] + 2 * mt * RP;
 #pragma unroll
         for (int v = 0; v < 4; v++) lds_add_i64(rr + v, round_scaled_i64(acc[v], wm[gt]));
       }
+    }
+#pragma unroll
+    for (int gt = 0; gt < 2; gt++) {
+      if (gt >= NG) break;
       if (q == 0 && mv[gt]) gadd_fix<kWsumFrac>(gwsum + (size_t)my[gt] * w + mx[gt], wgt);
     }
     };
@@ -1239,17 +1331,20 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
 // tile's references into the shared region, then the region is added into
 // num, two rows per wave and iteration (pixels no member touched hold exact
 // zeros and are skipped), and cleared for the next tile together with the
-// reference counter.  The region and counter must be zero on entry.
+// reference counter.  The region and counter must be zero on entry.  The
+// tile's pixels are staged in pix first.
 template <int STEP, class XF, int NGM>
 __device__ void filter_tile(const ImgDesc& d, const KParams& kp, int ty, int tx, int ch,
                             const typename XF::frag* tabB, const typename XF::frag* tabA, int64_t* wreg,
-                            int* lctr) {
+                            int* lctr, void* pix) {
   typedef FilterCfg<XF> C;
   const int S = STEP == 1 ? kp.S1 : kp.S2;
   const BlockGeom g = block_geom(d.h, d.w, d.nr, d.nc, S, kp.tile, ty, tx);
-  filter_tile_refs<STEP, XF, NGM>(d, kp, g, ch, tabB, tabA, wreg, lctr);
-  __syncthreads();
   const int RH = g.ny + 7, RW = g.nx + 7, RP = C::pitch(RW);
+  filter_stage_pixels<STEP, XF, 64 * FilterCfg<XF, NGM>::kWaves>(d, g, ch, RP, pix);
+  __syncthreads();
+  filter_tile_refs<STEP, XF, NGM>(d, kp, g, ch, tabB, tabA, wreg, lctr, pix);
+  __syncthreads();
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, l = lane_id();
   int64_t* gnum = d.num + (size_t)ch * d.h * d.w;
   for (int y0 = 2 * wave; y0 < RH; y0 += 2 * nw) {
@@ -1285,12 +1380,13 @@ __device__ void filter_block_single(const ImgDesc& d, const KParams& kp, int ch,
   frag* tabA = tabB + 16 * 64;
   int64_t* wreg = (int64_t*)(smem + C::tables());
   const size_t rb = C::region(S, kp.tile);
+  void* pix = (char*)wreg + rb + 16;
   filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
   filter_lds_clear(wreg, rb);
   __syncthreads();
   const int ntx = (d.nc + kp.tile - 1) / kp.tile;
   const int t = blockIdx.x;
-  filter_tile<STEP, XF, NGM>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg, (int*)(wreg + rb / 8));
+  filter_tile<STEP, XF, NGM>(d, kp, t / ntx, t % ntx, ch, tabB, tabA, wreg, (int*)(wreg + rb / 8), pix);
 }
 
 // image holding global item i: largest k with prefix[k] <= i
@@ -1313,6 +1409,7 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
   int64_t* wreg = (int64_t*)(smem + C::tables());
   const size_t rb = C::region(S, kp.tile);
   int* lctl = (int*)(wreg + rb / 8);  // reference counter, tile index
+  void* pix = (char*)wreg + rb + 16;
   filter_tables<XF>(tabB, tabA, STEP == 1 ? kp.f1 : kp.f2, STEP == 1 ? kp.i1 : kp.i2, kp.kaiser);
   filter_lds_clear(wreg, rb);
   __syncthreads();
@@ -1337,7 +1434,7 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
     const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
-    filter_tile<STEP, XF, NGM>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl);
+    filter_tile<STEP, XF, NGM>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl, pix);
     t += gridDim.x;
   }
   // every workgroup has drawn an index past the end; the last one to get
@@ -1506,11 +1603,12 @@ int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hip
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
       const int ngm = filter_ngm(stage == STAGE_FILTER1 ? kp.n1 : kp.n2);
-      const int nw = filter_waves(xform, S, kp.tile, ngm);
+      const int step = stage == STAGE_FILTER1 ? 1 : 2;
+      const int nw = filter_waves(xform, step, S, kp.tile, ngm);
       if (nw < 1) return -1;
       const int ntiles = ((d.nc + kp.tile - 1) / kp.tile) * ((d.nr + kp.tile - 1) / kp.tile);
       dim3 grid(ntiles, d.c);
-      size_t b = filter_lds_bytes(xform, S, kp.tile);
+      size_t b = filter_lds_bytes(xform, step, S, kp.tile);
 #define LAUNCH_F(STEP, XF)                                                                \
   do {                                                                                    \
     if (ngm == 1) {                                                                       \
@@ -1583,9 +1681,10 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
     case STAGE_FILTER2: {
       const int S = stage == STAGE_FILTER1 ? kp.S1 : kp.S2;
       const int ngm = filter_ngm(stage == STAGE_FILTER1 ? kp.n1 : kp.n2);
-      const int wv = filter_waves(xform, S, kp.tile, ngm);
+      const int step = stage == STAGE_FILTER1 ? 1 : 2;
+      const int wv = filter_waves(xform, step, S, kp.tile, ngm);
       if (wv < 1) return -1;
-      size_t b = filter_lds_bytes(xform, S, kp.tile);
+      size_t b = filter_lds_bytes(xform, step, S, kp.tile);
       int g = blocks > 0 ? std::min(blocks, nw) : nw;
       // dynamic tiles: as many workgroups as fit on the device at once
       const int per_cu = ngm == 1 ? 2 : stage == STAGE_FILTER1 && xform != 0 ? 3 : 2;
@@ -1620,8 +1719,8 @@ size_t stage_lds_bytes(int stage, int xform, const KParams& kp) {
     case STAGE_PREFILT: return prefilt_lds_bytes();
     case STAGE_MATCH1P: return match1p_lds_bytes(kp.S1);
     case STAGE_MATCH2: return match2_lds_bytes(kp.S2, kThreads / 64);
-    case STAGE_FILTER1: return filter_lds_bytes(xform, kp.S1, kp.tile);
-    case STAGE_FILTER2: return filter_lds_bytes(xform, kp.S2, kp.tile);
+    case STAGE_FILTER1: return filter_lds_bytes(xform, 1, kp.S1, kp.tile);
+    case STAGE_FILTER2: return filter_lds_bytes(xform, 2, kp.S2, kp.tile);
     default: return 0;
   }
 }
