@@ -1030,7 +1030,7 @@ __device__ inline void pixel_frags(const void* pix, int e, typename XF::frag& fa
 template <int STEP, class XF, int NGM>
 __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const BlockGeom& g, int ch,
                                  const typename XF::frag* __restrict__ tabB,
-                                 const typename XF::frag* __restrict__ tabA, int64_t* wreg, int* lctr,
+                                 const typename XF::frag* __restrict__ tabA, int64_t* __restrict__ wreg, int* lctr,
                                  const void* __restrict__ pix) {
   typedef typename XF::frag frag;
   typedef FilterCfg<XF> C;
@@ -1231,8 +1231,9 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
           for (int nt = 0; nt < 4; nt++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
-              const float b2 = D2b[tt][nt][v] * D2b[tt][nt][v];
-              const float W = b2 * __builtin_amdgcn_rcpf(b2 + sig2_n);
+              // B^2 / (B^2 + s) as 1 - s / (B^2 + s): one multiply-add less
+              const float den = __builtin_fmaf(D2b[tt][nt][v], D2b[tt][nt][v], sig2_n);
+              const float W = __builtin_fmaf(-sig2_n, __builtin_amdgcn_rcpf(den), 1.f);
               sw2 += W * W;
               D2[tt][nt][v] *= W;
             }
@@ -1254,7 +1255,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
         }
       }
       sw2 = wave_sum_uniform(sw2);
-      wgt = 1.f / fmaxf(sw2, 1.f / kMaxWeight);
+      wgt = __builtin_amdgcn_rcpf(fmaxf(sw2, 1.f / kMaxWeight));
     }
     if (l == 0) D2[0][0][0] -= off;
 
@@ -1299,17 +1300,27 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
       for (int ct = 0; ct < 4; ct++) b3[gt][ct] = XF::cvt(D3[ct][gt]);
       rb[gt] = wreg + (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
     }
-    // each table fragment is read once for both member tiles
-#pragma unroll
-    for (int mt = 0; mt < 4; mt++) {
+    // each table fragment is read once for both member tiles, one row tile
+    // ahead (so that the reads do not queue behind the row tile's atomics)
+    frag ta[2][4];
+    auto read_ta = [&](int mt, frag (&t)[4]) {
       const frag* ta0 = tabA + ((mt * 2) * 64 + l) * 2;
       const frag* ta1 = tabA + ((mt * 2 + 1) * 64 + l) * 2;
-      const frag t00 = ta0[0], t01 = ta0[1], t10 = ta1[0], t11 = ta1[1];
+      t[0] = ta0[0];
+      t[1] = ta0[1];
+      t[2] = ta1[0];
+      t[3] = ta1[1];
+    };
+    read_ta(0, ta[0]);
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+      if (mt < 3) read_ta(mt + 1, ta[(mt + 1) & 1]);
+      const frag(&t)[4] = ta[mt & 1];
 #pragma unroll
       for (int gt = 0; gt < 2; gt++) {
         if (gt >= NG) break;
-        f32x4 acc = XF::mma2(t00, t01, b3[gt][0], b3[gt][1], zero4());
-        acc = XF::mma2(t10, t11, b3[gt][2], b3[gt][3], acc);
+        f32x4 acc = XF::mma2(t[0], t[1], b3[gt][0], b3[gt][1], zero4());
+        acc = XF::mma2(t[2], t[3], b3[gt][2], b3[gt][3], acc);
         int64_t* rr = rb[gt] + 2 * mt * RP;
 #pragma unroll
         for (int v = 0; v < 4; v++) lds_add_i64(rr + v, round_scaled_i64(acc[v], wm[gt]));
