@@ -994,12 +994,15 @@ __device__ void filter_stage_pixels(const ImgDesc& d, const BlockGeom& g, int ch
 }
 
 // The A-operand fragment of 4 adjacent staged pixels from position e: the
-// noisy values into fa and, in step 2, the basic ones into fb.
+// noisy values into fa and, in step 2, the basic ones into fb.  pix_lds is
+// the staged pixels' LDS byte address as an opaque uniform value, so that the
+// compiler folds the offsets of the four dwords into the read instructions.
 template <int STEP, class XF>
-__device__ inline void pixel_frags(const void* pix, int e, typename XF::frag& fa, typename XF::frag& fb) {
+__device__ inline void pixel_frags(const void* pix, uint32_t pix_lds, int e, typename XF::frag& fa,
+                                   typename XF::frag& fb) {
   typedef typename XF::frag frag;
   if constexpr (sizeof(frag) == 8) {
-    const uint32_t* P = (const uint32_t*)pix + e;
+    const BM3D_LDS uint32_t* P = (const BM3D_LDS uint32_t*)(uintptr_t)(pix_lds + 4u * (uint32_t)e);
     if (STEP == 1) {
       const uint2 u = {P[0], P[2]};
       fa = __builtin_bit_cast(frag, u);
@@ -1080,6 +1083,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
   // fb (step 2).  With 16-bit operands they are read one reference ahead,
   // with FP32 operands (twice the registers) when the group starts.
   constexpr bool kEarlyFrags = sizeof(frag) == 8;
+  const uint32_t pix_lds = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(const BM3D_LDS char*)pix);
   frag fa[2][4], fb[2][4];
   auto read_frags = [&](int n, const int (&my)[2], const int (&mx)[2]) {
 #pragma unroll
@@ -1087,7 +1091,7 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
       if (gt == 1 && n <= 16) break;
       const int e0 = (my[gt] - g.uy0 + (q >> 1)) * RP + (mx[gt] - g.ux0) + 4 * (q & 1);
 #pragma unroll
-      for (int kt = 0; kt < 4; kt++) pixel_frags<STEP, XF>(pix, e0 + 2 * kt * RP, fa[gt][kt], fb[gt][kt]);
+      for (int kt = 0; kt < 4; kt++) pixel_frags<STEP, XF>(pix, pix_lds, e0 + 2 * kt * RP, fa[gt][kt], fb[gt][kt]);
     }
   };
   bool mv_nx[2];
