@@ -88,16 +88,22 @@ def source_sha(family):
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, images, tile, family="bm3d"):
+def measured_traffic(kernel, images, tile, family="bm3d", match_refs=8):
     """HBM bytes per launch of `kernel` from the committed counter runs
     (profiles/hbm_traffic_*.json), if they were taken on the current sources
-    of its kernel family with the same tile setting; None otherwise."""
+    of its kernel family with the settings that shape its accesses (the
+    filter tile for the filters, the references per step-1 matching pass for
+    match1); None otherwise."""
     import glob
     sha = source_sha(family)
     for path in glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.json")):
         rec = json.load(open(path))
+        if kernel.startswith("filter") and rec.get("tile_refs") != tile:
+            continue
+        if kernel == "match1" and rec.get("match_refs", 8) != match_refs:
+            continue
         if (rec.get("family", "bm3d") == family and rec.get("source_sha") == sha
-                and rec.get("tile_refs") == tile and kernel in rec.get("kernels", {})):
+                and kernel in rec.get("kernels", {})):
             k = rec["kernels"][kernel]
             return images * (k["fetch_bytes_per_image"] + k["write_bytes_per_image"])
     return None
@@ -993,7 +999,8 @@ def main():
     achieved = work[dom] / (stage_ms[dom] * 1e-3)
     roof = {"bound": bound, "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
             "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic(dom, B, p.tile_refs) if args.xform == "bf16" else None,
+            "traffic": (measured_traffic(dom, B, p.tile_refs, match_refs=p.match_refs)
+                        if args.xform == "bf16" else None),
             "ms_per_launch": stage_ms[dom], "work_per_launch": work[dom],
             "work_model": {"match1": "S^2 * 64 int8 multiply-adds per reference",
                            "match2": "S^2 * 64 FP32 multiply-adds per reference (direct differences)",
