@@ -849,8 +849,11 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 template <class XF, int NGM = 2> struct FilterCfg {
   typedef typename XF::frag frag;
   static constexpr int kWaves = NGM == 1 ? 8 : 4;  // waves per workgroup
-  // workgroups per CU the registers allow
-  static constexpr int per_cu(int step) { return NGM == 1 ? 2 : step == 1 && sizeof(frag) == 8 ? 3 : 2; }
+  // workgroups per CU the registers are budgeted for (the FP32 form's
+  // tables and staged pixels leave room for one at the autotuner's tiles)
+  static constexpr int per_cu(int step) {
+    return sizeof(frag) == 16 ? 1 : NGM == 1 ? 2 : step == 1 ? 3 : 2;
+  }
   static constexpr int waves_per_simd(int step) { return per_cu(step) * kWaves / 4; }
   static __host__ __device__ size_t tables() { return (size_t)32 * 64 * sizeof(frag); }
   static __host__ __device__ int rnum(int S, int T) { return 3 * (T - 1) + S + 7; }
@@ -1110,8 +1113,14 @@ __device__ void filter_tile_refs(const ImgDesc& d, const KParams& kp, const Bloc
       xx = gi - yy * w;
       // a member must lie in the tile's search region (true for any grouping
       // made with the same window rule); anything else is ignored
-      bool inside = gi >= 0 && yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
-      mv_nx[gt] = gm < n_nx && inside;
+      // (16-bit forms: bitwise, without branches; the FP32 form keeps the
+      // short-circuit form, which needs fewer registers there)
+      bool inside;
+      if constexpr (kEarlyFrags)
+        inside = (gi >= 0) & (yy >= g.uy0) & (yy < g.uy0 + g.ny) & (xx >= g.ux0) & (xx < g.ux0 + g.nx);
+      else
+        inside = gi >= 0 && yy >= g.uy0 && yy < g.uy0 + g.ny && xx >= g.ux0 && xx < g.ux0 + g.nx;
+      mv_nx[gt] = (gm < n_nx) & inside;
       my_nx[gt] = inside ? yy : g.uy0;
       mx_nx[gt] = inside ? xx : g.ux0;
     }
@@ -1702,7 +1711,7 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
       size_t b = filter_lds_bytes(xform, step, S, kp.tile);
       int g = blocks > 0 ? std::min(blocks, nw) : nw;
       // dynamic tiles: as many workgroups as fit on the device at once
-      const int per_cu = ngm == 1 ? 2 : stage == STAGE_FILTER1 && xform != 0 ? 3 : 2;
+      const int per_cu = xform == 0 ? 1 : ngm == 1 ? 2 : stage == STAGE_FILTER1 ? 3 : 2;
       if (br.ctr && cus > 0) g = std::min(nw, cus * std::max(1, std::min(per_cu, (int)(kLdsBytes / b))));
 #define LAUNCH_FB(STEP, XF)                                                               \
   do {                                                                                    \
