@@ -160,9 +160,10 @@ constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 // ----------------------------------------------------- wave primitives ---
 __device__ inline int lane_id() { return __lane_id(); }
 
-__device__ inline uint64_t lanemask_lt() {
-  int l = lane_id();
-  return l == 0 ? 0ull : (~0ull >> (64 - l));
+// add + the number of set bits of the wave mask b below this lane
+// (v_mbcnt_lo / v_mbcnt_hi: two instructions)
+__device__ inline int mbcnt(uint64_t b, int add) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, (uint32_t)add));
 }
 
 // Cross-lane moves in registers only (no LDS traffic): DPP within rows of 16
@@ -384,7 +385,6 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
   const int l = lane_id();
   K theta[NR];
   int base[NR];
-  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < NR; r++) {
     uint32_t mn[1] = {k[r][0]};
@@ -408,7 +408,7 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
     for (int r = 0; r < NR; r++) {
       const bool p = n[r] > 1 && k[r][t] <= theta[r] && k[r][t] != NONE;
       const uint64_t b = __ballot(p);
-      buf[r][p ? base[r] + __popcll(b & lt) : spare + l] = k[r][t];
+      buf[r][p ? mbcnt(b, base[r]) : spare + l] = k[r][t];
       base[r] += __popcll(b);
     }
   }
@@ -472,12 +472,11 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], int wi0, int ws
     if (n == 1) return 1;
   }
   int base = 0;
-  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int t = 0; t < 16; t++) {
     const bool p = db[t] != NONE && (db[t] >> 16) <= th;
     const uint64_t b = __ballot(p);
-    buf[p ? base + __popcll(b & lt) : spare + l] = ((uint64_t)db[t] << 32) | (uint32_t)(wi0 + wstep * t);
+    buf[p ? mbcnt(b, base) : spare + l] = ((uint64_t)db[t] << 32) | (uint32_t)(wi0 + wstep * t);
     base += __popcll(b);
   }
   wave_lds_sync();

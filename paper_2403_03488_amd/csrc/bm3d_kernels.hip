@@ -1533,12 +1533,13 @@ __global__ void __launch_bounds__(kThreads) kb_prefilt(BatchRef br, KParams kp) 
   }
 }
 
-// The prefiltered matcher's LDS allows four workgroups per CU and the
-// step-2 matcher's three; their register budgets are held to match, so the
-// compiler does not trade occupancy for hoisted LDS reads.
+// The step-2 matcher's LDS allows three workgroups per CU; its register
+// budget is held to match, so the compiler does not trade occupancy for
+// hoisted LDS reads.  The prefiltered matcher's LDS would allow four, but
+// at that budget it spills; it runs at three, without spills.
 // PR: step-1 references per matching pass (unused by the other steps).
 template <int STEP, int PR = 8>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 4 : STEP == 2 ? 3 : 1)))
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(STEP == 3 ? 3 : STEP == 2 ? 3 : 1)))
 kb_match(BatchRef br, KParams kp) {
   extern __shared__ __align__(16) char smem[];
   for (int i = br.begin + blockIdx.x; i < br.end; i += gridDim.x) {
