@@ -11,6 +11,8 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("bm3d_kernels.hip", "bm3d_api
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results straight into VGPRs (no AGPR round trip)
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I", os.path.join(ROOT, "include")]
 
 
