@@ -401,12 +401,15 @@ __device__ void select_group(const K (&k)[NR][16], int nmax, K* const (&buf)[NR]
     }
     base[r] = 0;
   }
-  // compact the survivors (candidates with key <= theta) into buf
+  // compact the survivors (candidates with key <= theta) into buf; with
+  // theta = NONE every candidate survives, and NONE itself never does
+#pragma unroll
+  for (int r = 0; r < NR; r++) theta[r] = theta[r] == NONE ? NONE - 1 : theta[r];
 #pragma unroll
   for (int t = 0; t < 16; t++) {
 #pragma unroll
     for (int r = 0; r < NR; r++) {
-      const bool p = n[r] > 1 && k[r][t] <= theta[r] && k[r][t] != NONE;
+      const bool p = n[r] > 1 && k[r][t] <= theta[r];
       const uint64_t b = __ballot(p);
       buf[r][p ? mbcnt(b, base[r]) : spare + l] = k[r][t];
       base[r] += __popcll(b);
@@ -472,9 +475,12 @@ __device__ inline int select_group_f32(const uint32_t (&db)[16], int wi0, int ws
     if (n == 1) return 1;
   }
   int base = 0;
+  // non-candidates (all ones) never pass; candidates are finite distances,
+  // whose top 16 bits are at most 0x7F80
+  const uint32_t th2 = th < 0xFFFEu ? th : 0xFFFEu;
 #pragma unroll
   for (int t = 0; t < 16; t++) {
-    const bool p = db[t] != NONE && (db[t] >> 16) <= th;
+    const bool p = (db[t] >> 16) <= th2;
     const uint64_t b = __ballot(p);
     buf[p ? mbcnt(b, base) : spare + l] = ((uint64_t)db[t] << 32) | (uint32_t)(wi0 + wstep * t);
     base += __popcll(b);
