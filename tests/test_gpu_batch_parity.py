@@ -219,6 +219,27 @@ def test_batch_bf16_within_005db_of_fp32(B, key):
 
 
 @pytest.mark.parametrize("xform", [0, 1])
+def test_batch_group_sizes_equal_single(B, xform):
+    """Group-size limits 32 (step 1) and 16 (step 2): the batched filters
+    built for the other member-tile limits equal the single-image path."""
+    samples = mixed()[:8]
+    p = B.params_default(25.0, xform=xform, flags=B.FLAG_SIGMA_PROFILE)
+    p.tile_refs, p.n_ht, p.n_wie = TILE, 32, 16
+    imgs = [dev(s.noisy) for s in samples]
+    outs = [torch.empty(s.noisy.shape, dtype=torch.float32, device="cuda") for s in samples]
+    plan = B.Batch(imgs, outs, [s.sigma for s in samples], p)
+    replay_graph(plan, 1)
+    for i, (s, im, o) in enumerate(zip(samples, imgs, outs)):
+        q = p.copy()
+        q.tau_ht, q.tau_wie = taus(s.sigma)
+        q.flags = 0
+        single = B.denoise(im, s.sigma, q)
+        np.testing.assert_array_equal(host(single), host(o), err_msg="image %d" % i)
+    log("batch == single bit for bit with groups 32/16: xform %d, %d images" % (xform, len(samples)))
+    plan.close()
+
+
+@pytest.mark.parametrize("xform", [0, 1])
 @pytest.mark.parametrize("persistent", [0, 2])
 def test_batch_equals_single_bit_for_bit(B, xform, persistent):
     samples = mixed()[:24]

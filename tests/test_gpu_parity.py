@@ -289,7 +289,7 @@ def staged_step2(B, planar, basic, sigma, p, idx2, cnt2, shape):
     return out
 
 
-def anchored_check(B, img, sigma, S, ref, inter, margin, onk, what):
+def anchored_check(B, img, sigma, S, ref, inter, margin, onk, what, **kw):
     """The fused single-image path (bm3d_denoise) against the oracle.
 
     1. Its step-1 groups (read from its workspace) equal the oracle's bit
@@ -300,10 +300,11 @@ def anchored_check(B, img, sigma, S, ref, inter, margin, onk, what):
     4. Anchored: step 2 with the oracle's groups (and the fused run's basic
        estimate) is within 1e-3 of the oracle's final image away from the
        pixels a near-tie can reach.
+    kw: further bm3d_params fields (the oracle's run must use the same).
     Returns the fused output."""
     c = 1 if img.ndim == 2 else 3
     h, w = img.shape[:2]
-    p = gparams(B, sigma, S, flags=B.FLAG_DEBUG_NKEPT)
+    p = gparams(B, sigma, S, flags=B.FLAG_DEBUG_NKEPT, **kw)
     ws = torch.empty(B.workspace_size(h, w, c, p), dtype=torch.uint8, device="cuda")
     gimg = dev(img)
     out = B.denoise(gimg, sigma, p, workspace=ws)
@@ -359,6 +360,25 @@ def test_tiny_and_ragged_anchored(B, shape):
     _, _, margin, onk = oracle.collab_filter(planar, None, sigma, 1, inter["idx1"], inter["cnt1"], op,
                                              want_margin=True)
     anchored_check(B, img, sigma, S, ref, inter, margin, onk, "tiny %s" % (shape,))
+
+
+# Group-size limits other than the defaults (16 / 32): the filter bodies
+# built for one member tile (n <= 16) in step 2 and for two (n = 32) in
+# step 1, and small groups, against the oracle, grey and colour.
+@pytest.mark.parametrize("n_ht,n_wie,c", [(32, 16, 1), (8, 4, 1), (2, 32, 1), (32, 8, 3)])
+def test_group_sizes_anchored(B, n_ht, n_wie, c):
+    shape = (64, 80) if c == 1 else (48, 72, 3)
+    img = synth.small_gray(index=5, h=shape[0], w=shape[1]).noisy if c == 1 else \
+        np.random.default_rng(11).integers(0, 256, shape).astype(np.uint8)
+    sigma, S = 25.0, 16
+    op = ph.oracle_params(sigma, S)
+    op.n_ht, op.n_wie = n_ht, n_wie
+    ref, inter = oracle.denoise(img, sigma, op, want_intermediates=True)
+    planar, _ = oracle.prepare(img)
+    _, _, margin, onk = oracle.collab_filter(planar, None, sigma, 1, inter["idx1"], inter["cnt1"], op,
+                                             want_margin=True)
+    anchored_check(B, img, sigma, S, ref, inter, margin, onk, "groups %d/%d c=%d" % (n_ht, n_wie, c),
+                   n_ht=n_ht, n_wie=n_wie)
 
 
 @pytest.mark.parametrize("case", ["small_gray", "colour_s25"])
