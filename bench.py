@@ -908,8 +908,9 @@ def main():
     if args.quick:
         args.no_autotune = args.no_cpu_baseline = True
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the design notes for how the work would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "every image is independent, so a batch would shard by image across GPUs",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch64":
         return run_batch64(args)
