@@ -449,6 +449,7 @@ struct bm3d_batch {
   size_t ws_bytes = 0;
   std::vector<size_t> base;  // offset of each image's workspace in ws
   int* ctr = nullptr;  // dynamic filter-tile counter pair (zero between launches)
+  TileRef* order = nullptr;  // the filter items, largest tiles first
   int cus = 256;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -485,7 +486,10 @@ int batch_stage(bm3d_batch* b, int stage, int i0, int i1, hipStream_t s) {
   }
   const int L = list_of_stage(stage);
   BatchRef br{b->dd, b->dprefix[L], b->n, b->hprefix[L][i0], b->hprefix[L][i1]};
-  if (stage == STAGE_FILTER1 || stage == STAGE_FILTER2) br.ctr = b->ctr;
+  if (stage == STAGE_FILTER1 || stage == STAGE_FILTER2) {
+    br.ctr = b->ctr;
+    if (i0 == 0 && i1 == b->n) br.order = b->order;  // the whole batch: largest tiles first
+  }
   int r = launch_batch(stage, b->p.xform, br, b->kp, persistent_blocks(b->p, b->cus), s, want_sync(&b->p),
                        b->cus);
   return r == 0 ? BM3D_OK : BM3D_ERR_HIP;
@@ -526,9 +530,30 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
     b->hd.push_back(d);
   }
   fill_prefix(b->hd.data(), n, b->kp, b->hprefix);
+  // The filter items of the whole batch, the tiles with the most references
+  // first (ties in image-major order): the dynamic schedule ends on the
+  // smallest tiles, which shortens the time the last workgroups run alone.
+  std::vector<TileRef> order;
+  {
+    std::vector<std::pair<int, TileRef>> items;
+    const int T = b->kp.tile;
+    for (int i = 0; i < n; i++) {
+      const ImgDesc& d = b->hd[i];
+      const int ntx = (d.nc + T - 1) / T, nty = (d.nr + T - 1) / T;
+      for (int j = 0; j < b->hprefix[LIST_FILTER][i + 1] - b->hprefix[LIST_FILTER][i]; j++) {
+        const int r = j % (ntx * nty), ty = r / ntx, tx = r % ntx;
+        const int refs = std::min(T, d.nr - T * ty) * std::min(T, d.nc - T * tx);
+        items.push_back({refs, TileRef{i, j}});
+      }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const std::pair<int, TileRef>& a, const std::pair<int, TileRef>& c) { return a.first > c.first; });
+    for (const auto& it : items) order.push_back(it.second);
+  }
   const size_t desc_bytes = align_up(sizeof(ImgDesc) * n);
   const size_t pre_bytes = align_up(sizeof(int) * (n + 1));
-  const size_t all = tot + desc_bytes + LIST_KINDS * pre_bytes + 256;
+  const size_t order_bytes = align_up(sizeof(TileRef) * std::max<size_t>(1, order.size()));
+  const size_t all = tot + desc_bytes + LIST_KINDS * pre_bytes + 256 + order_bytes;
   if (hipMalloc((void**)&b->ws, all) != hipSuccess) {
     delete b;
     return BM3D_ERR_NOMEM;
@@ -538,7 +563,10 @@ extern "C" int bm3d_batch_create(const bm3d_image_desc* imgs, int n, const bm3d_
   b->dd = (ImgDesc*)(b->ws + tot);
   for (int L = 0; L < LIST_KINDS; L++) b->dprefix[L] = (int*)(b->ws + tot + desc_bytes + L * pre_bytes);
   b->ctr = (int*)(b->ws + tot + desc_bytes + LIST_KINDS * pre_bytes);
+  b->order = (TileRef*)(b->ws + tot + desc_bytes + LIST_KINDS * pre_bytes + 256);
   bool ok = hipMemcpy(b->dd, b->hd.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && (order.empty() ||
+              hipMemcpy(b->order, order.data(), sizeof(TileRef) * order.size(), hipMemcpyHostToDevice) == hipSuccess);
   ok = ok && hipMemset(b->ctr, 0, 2 * sizeof(int)) == hipSuccess;
   for (int L = 0; L < LIST_KINDS && ok; L++)
     ok = hipMemcpy(b->dprefix[L], b->hprefix[L].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) ==

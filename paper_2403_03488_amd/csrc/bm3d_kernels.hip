@@ -1453,9 +1453,16 @@ __device__ void filter_block_batch(BatchRef br, const KParams& kp, char* smem) {
     t = __builtin_amdgcn_readfirstlane(lctl[1]);
     if (t >= total) break;
     const int i = br.begin + t;
-    const int im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
+    int im, j;
+    if (br.order) {
+      const TileRef o = ldc(br.order + i);
+      im = o.img;
+      j = o.item;
+    } else {
+      im = __builtin_amdgcn_readfirstlane(find_img(br.prefix, br.nimg, i));
+      j = i - br.prefix[im];
+    }
     const ImgDesc d = ldc(br.ds + im);
-    const int j = i - br.prefix[im];
     const int ntx = (d.nc + kp.tile - 1) / kp.tile, nty = (d.nr + kp.tile - 1) / kp.tile;
     const int ch = j / (ntx * nty), r = j - ch * (ntx * nty);
     filter_tile<STEP, XF, NGM>(d, kp, r / ntx, r % ntx, ch, tabB, tabA, wreg, lctl, pix);

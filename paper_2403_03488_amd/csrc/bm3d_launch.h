@@ -56,6 +56,11 @@ __host__ __device__ inline int items_of(int list, const ImgDesc& d, int tile, in
   }
 }
 
+// A filter work item: image and the image's own item index.
+struct TileRef {
+  int img, item;
+};
+
 struct BatchRef {
   const ImgDesc* ds;   // device descriptors of the images
   const int* prefix;   // device prefix item counts for the stage's list kind (nimg+1)
@@ -66,6 +71,9 @@ struct BatchRef {
   // last wave to finish zeroes the pair again (launches using one pair must
   // not overlap)
   int* ctr = nullptr;
+  // optional device list of the filter items in the order they are handed
+  // out (item i of the launch is order[i]); without one, image-major order
+  const TileRef* order = nullptr;
 };
 
 int launch_single(int stage, int xform, const ImgDesc& d, const KParams& kp, hipStream_t s, bool sync);
