@@ -838,14 +838,17 @@ __device__ void match1p_block(const ImgDesc& d, const KParams& kp, int by, int b
 // the per-position sum of group weights, so the filter adds each member's
 // weight once, at its corner, into a global weight map (wsum); the
 // aggregation forms the denominator from it.
+// Before a tile's references are filtered, its pixels are staged in LDS in
+// operand form (filter_stage_pixels), so member gathers are LDS reads.
 // NGM is the largest group size in member tiles of 16 the kernel is built
 // for (1: n <= 16, as step 1 with its default size).  Without the 32-member
 // body a filter needs under 128 registers: workgroups of eight waves, two
 // per CU (four waves per SIMD).  With it, four waves per workgroup and two
 // or three workgroups per CU: step 1 in a 16-bit form fits 168 registers
-// per lane (3 waves per SIMD), the others need up to 256.  While one
-// workgroup waits for its slowest wave or flushes, the others keep the
-// SIMDs busy.
+// per lane (3 waves per SIMD), the others need up to 256.  The FP32 form's
+// tables and staged pixels leave LDS for one workgroup per CU at the usual
+// tiles, and its registers are budgeted for that.  While one workgroup
+// waits for its slowest wave or flushes, the others keep the SIMDs busy.
 template <class XF, int NGM = 2> struct FilterCfg {
   typedef typename XF::frag frag;
   static constexpr int kWaves = NGM == 1 ? 8 : 4;  // waves per workgroup
