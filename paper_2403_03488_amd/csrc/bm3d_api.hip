@@ -610,9 +610,10 @@ extern "C" int bm3d_batch_run_stages(bm3d_batch* b, int i0, int i1, int first, i
   hipStream_t s = (hipStream_t)stream;
   int e;
   for (int st = first; st <= last; st++) {
-    if ((e = batch_stage(b, st, i0, i1, s))) return e;
-    // the accumulators start from zero before each filtering step
-    if (st == STAGE_PREP || st == STAGE_AGG1)
+    // the accumulators start from zero before each filtering step (before
+    // step 1 zeroed by the preparation itself)
+    if ((e = batch_stage(b, st == STAGE_PREP ? STAGE_PREP_FILL : st, i0, i1, s))) return e;
+    if (st == STAGE_AGG1)
       if ((e = batch_stage(b, STAGE_FILL, i0, i1, s))) return e;
   }
   return BM3D_OK;
@@ -775,7 +776,8 @@ extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
     const int* hfill = (const int*)((const char*)hpre + align_up(sizeof(int) * (m + 1)));
     BatchRef br{dd, pre, m, 0, hpre[m]};
     if (stg == STAGE_FILTER1 || stg == STAGE_FILTER2) br.ctr = (int*)(s->dev[k] + s->table_bytes);
-    int launch_stage = stg;
+    // the preparation zeroes the step-1 accumulators itself (same pixel list)
+    int launch_stage = stg == STAGE_PREP ? STAGE_PREP_FILL : stg;
     if (stg == STAGE_MATCH1 && s->kp.prefilter) {  // thresholded spectra first, on their own list
       const int* ppre = (const int*)((const char*)pfill + align_up(sizeof(int) * (m + 1)));
       const int* hppre = (const int*)((const char*)hfill + align_up(sizeof(int) * (m + 1)));
@@ -785,7 +787,7 @@ extern "C" int bm3d_server_tick(bm3d_server* s, const bm3d_request* reqs, int n,
       launch_stage = STAGE_MATCH1P;
     }
     if (launch_batch(launch_stage, s->p.xform, br, s->kp, blocks, st, want_sync(&s->p), s->cus)) return BM3D_ERR_HIP;
-    if (stg == STAGE_PREP || stg == STAGE_AGG1) {
+    if (stg == STAGE_AGG1) {
       BatchRef bf{dd, pfill, m, 0, hfill[m]};
       if (launch_batch(STAGE_FILL, s->p.xform, bf, s->kp, blocks, st, want_sync(&s->p))) return BM3D_ERR_HIP;
     }

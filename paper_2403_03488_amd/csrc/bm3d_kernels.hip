@@ -41,12 +41,19 @@ __device__ inline float channel_centre(int c, int ch) {
 }
 
 // =================================================================== prep ==
-__device__ void prep_chunk(const ImgDesc& d, int chunk) {
+// zero_acc: also zero num and wsum of every channel at the chunk's pixels
+// (what a separate fill would do, without its launch)
+__device__ void prep_chunk(const ImgDesc& d, int chunk, bool zero_acc = false) {
   const size_t hw = (size_t)d.h * d.w;
   const size_t p0 = (size_t)chunk * kChunk;
   for (int k = 0; k < 4; k++) {
     size_t p = p0 + (size_t)k * kThreads + threadIdx.x;
     if (p >= hw) return;
+    if (zero_acc)
+      for (int ch = 0; ch < d.c; ch++) {
+        d.num[ch * hw + p] = 0;
+        d.wsum[ch * hw + p] = 0;
+      }
     if (d.c == 1) {
       uint8_t v = d.img[p];
       d.planar[p] = (float)v;
@@ -1514,6 +1521,7 @@ __global__ void __launch_bounds__(kThreads) kb_elem(int stage, BatchRef br, KPar
     const ImgDesc d = ldc(br.ds + im);  // by value: kept in registers
     const int j = i - br.prefix[im];
     if (stage == STAGE_PREP) prep_chunk(d, j);
+    else if (stage == STAGE_PREP_FILL) prep_chunk(d, j, true);
     else if (stage == STAGE_AGG1) agg1_tile(d, kp, j, sh);
     else if (stage == STAGE_AGG2) agg2_tile(d, kp, j, sh);
     else if (stage == STAGE_FILL) fill_chunk(d, j);
@@ -1677,6 +1685,7 @@ int launch_batch(int stage, int xform, const BatchRef& br, const KParams& kp, in
   int grid = (blocks <= 0 || blocks > nw) ? nw : blocks;
   switch (stage) {
     case STAGE_PREP:
+    case STAGE_PREP_FILL:
     case STAGE_AGG1:
     case STAGE_AGG2:
     case STAGE_FILL:

@@ -18,7 +18,8 @@ enum Stage {
   STAGE_FILL = 7,     // zero num/den
   STAGE_LUM = 8,      // step-2 luminance from a planar basic estimate
   STAGE_PREFILT = 9,  // prefiltered step-1 matching: thresholded 2-D spectra
-  STAGE_MATCH1P = 10  // prefiltered step-1 matching: grouping on them
+  STAGE_MATCH1P = 10, // prefiltered step-1 matching: grouping on them
+  STAGE_PREP_FILL = 11  // prep, and num/wsum of the same pixels zeroed (batched passes)
 };
 
 // Batched launches decode their work arithmetically: for every image the
@@ -34,7 +35,7 @@ constexpr int kPrefiltItemPositions = 64;
 
 __host__ __device__ inline int list_of_stage(int stage) {
   switch (stage) {
-    case STAGE_PREP: case STAGE_LUM: return LIST_PIX;
+    case STAGE_PREP: case STAGE_PREP_FILL: case STAGE_LUM: return LIST_PIX;
     case STAGE_AGG1: case STAGE_AGG2: return LIST_AGG;
     case STAGE_FILL: return LIST_PLANE;
     case STAGE_MATCH1: case STAGE_MATCH2: case STAGE_MATCH1P: return LIST_MATCH;
